@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput of the fused Gray-Scott step on one MI355X.
+
+Workload (default): one GPU's weak-scaling share at L=512 (periodic 512^3
+cells), Du=0.2, Dv=0.1, F=0.02, k=0.048, dt=1, noise 1e-7 (Philox-keyed),
+cube initial state, FP64 storage. A "step" is one time step of the whole
+grid: neighbour gather, Laplacian, reaction/feed/kill, noise, Euler update
+and the ping-pong (one launch of the step kernel). Inputs are resident in
+HBM before timing starts.
+
+Prints ONE JSON line: metric/value (G cell-updates/s), roofline of the step
+kernel (algorithmic bytes per launch / average launch time from HIP events
+on the kernel's stream), the FP32/BF16/FP16 storage variants at the same
+workload, and the CPU oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_CELL = {"f64": 32, "f32": 16, "bf16": 8, "f16": 8}  # read u,v + write u,v once per step
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_CELL))
+    ap.add_argument("--L", type=int, default=512)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--variants", default="f32,bf16,f16", help="other storage types to time ('' for none)")
+    ap.add_argument("--variant-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    return ap.parse_args()
+
+
+def time_steps(torch, sim, steps, warmup):
+    """Average per-launch time (ms) of `steps` step launches, HIP events on the
+    stream the library launches on (torch's current stream, bound at init)."""
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    sim.step(steps)
+    e1.record(st)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def traffic_for(path, kernel_key):
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        return t.get(kernel_key)
+    except (OSError, ValueError):
+        return None
+
+
+def cpu_baseline(L, p, budget_s):
+    """The FP64 oracle on the host cores: whole-grid steps of the same
+    workload until the time budget is used (at least one step)."""
+    from oracle import oracle as O
+    threads = O.max_threads()
+    u, v = O.init_cube(L=L)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        u, v = O.run(u, v, 1, step0=done, **p)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=round(L ** 3 * done / el / 1e9, 4), unit="Gcell-updates/s", cores=threads, kind="oracle",
+                sample=f"{done} whole-grid FP64 steps of the {L}^3 noisy workload, {el:.1f} s on {threads} threads")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported "
+              "(the step runs on one MI355X; multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2309_10292_amd import gs
+    from synth import workload
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    gs.load()
+    wl = workload("weak_share_l512")
+    L = a.L
+    p = {k: wl[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
+
+    def measure(storage, steps, warmup):
+        with gs.Sim(L, L, L, storage=storage, tile=a.tile, cube_side=wl["cube_side"], **p) as s:
+            ms = time_steps(torch, s, steps, warmup)
+            d = s.diagnostics(allow_nonfinite=True)
+        return ms, d
+
+    ms, diag = measure(a.storage, a.steps, a.warmup)
+    cells = L ** 3
+    value = cells / (ms * 1e-3) / 1e9
+    bpc = BYTES_PER_CELL[a.storage]
+    achieved = bpc * cells / (ms * 1e-3) / 1e9
+    kernel_key = f"step_{a.storage}_L{L}"
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_for(a.traffic_file, kernel_key),
+                kernel="stencil_tile (fused step)", bytes_per_cell=bpc, launches=a.steps)
+
+    variants = {}
+    for sv in [x for x in a.variants.split(",") if x and x != a.storage]:
+        vms, vd = measure(sv, a.variant_steps, a.warmup)
+        vach = BYTES_PER_CELL[sv] * cells / (vms * 1e-3) / 1e9
+        variants[sv] = dict(value=round(cells / (vms * 1e-3) / 1e9, 3), ms_per_step=round(vms, 5),
+                            hbm_gbs=round(vach, 1), frac=round(vach / HBM_PEAK_GBS, 4), steps=a.variant_steps,
+                            bytes_per_cell=BYTES_PER_CELL[sv])
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(L, p, a.cpu_seconds)
+
+    out = {
+        "metric": "Gcell-updates/s (fused Gray-Scott step, both fields)",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.storage,
+        "data": "synthetic (cube initial state, Philox noise)",
+        "config": {"workload": f"gray-scott periodic {L}^3, noise 1e-7, {a.storage} storage (one GPU's weak-scaling share)",
+                   "L": L, "Du": p["Du"], "Dv": p["Dv"], "F": p["F"], "k": p["k"], "dt": p["dt"],
+                   "noise": p["noise"], "tile": a.tile},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "diagnostics_after": {k: diag[k] for k in ("sum_u", "sum_v", "min_u", "max_u", "min_v", "max_v", "nonfinite")},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

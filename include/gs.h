@@ -1,0 +1,166 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) Gray-Scott library, libgs.so.
+ *
+ * The library advances the two coupled Gray-Scott fields u, v of the paper's
+ * Section 3.1 on a periodic 3-D grid:
+ *   Eq. 1a/1b  dU/dt = Du lap(U) - U V^2 + F (1 - U) + n r
+ *              dV/dt = Dv lap(V) + U V^2 - (F + k) V
+ *   Eq. 2a/2b  forward Euler in time, Jacobi (level t+1 from level t only)
+ *   Eq. 3      7-point Laplacian in normalised units: (sum of six neighbours - 6 c) / 6
+ *
+ * Conventions shared by every entry point:
+ *   - Layout: a field is nz*ny*nx contiguous elements, x fastest:
+ *     idx = x + nx * (y + ny * z). Boundaries are periodic in x, y and z.
+ *   - Device pointers are HIP device allocations (hipMalloc or PyTorch's
+ *     allocator) on the current HIP device, aligned to 256 bytes. The caller
+ *     owns all field and workspace memory; the library never frees it.
+ *   - Host pointers are ordinary host memory.
+ *   - `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; calls documented as
+ *     synchronising wait for that stream only.
+ *   - Every call returns a gs_status. Arguments are validated before any HIP
+ *     call is made, so validation errors leave device state untouched.
+ *     gs_last_error() returns a thread-local message for the last failure.
+ *   - A handle is used from one host thread at a time; distinct handles are
+ *     independent.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = -1, /* NULL/misaligned pointer, non-finite or negative coefficient, bad size */
+    GS_ERR_UNSUPPORTED = -2, /* well-formed request outside what the kernels handle (e.g. nx % 8 != 0) */
+    GS_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed (message has hipGetErrorString) */
+    GS_ERR_NONFINITE = -4,   /* gs_diagnostics found NaN or Inf in the fields */
+    GS_ERR_STATE = -5        /* NULL or destroyed handle */
+} gs_status;
+
+/* Storage type of the fields in device memory. GS_F64 computes in FP64 and
+ * reproduces the FP64 definition of the step bit for bit; the other types
+ * compute in FP32 (Laplacian neighbour sum compensated) and round each stored
+ * value to nearest-even. */
+typedef enum gs_dtype { GS_F64 = 0, GS_F32 = 1, GS_BF16 = 2, GS_F16 = 3 } gs_dtype;
+
+typedef enum gs_init_mode {
+    GS_INIT_NONE = 0, /* the caller has filled u0, v0 (storage type) */
+    GS_INIT_CUBE = 1  /* u = 1, v = 0, and the axis-aligned cube of side cube_side with lower
+                         corner floor((n - cube_side) / 2) per axis set to (cube_u, cube_v) */
+} gs_init_mode;
+
+/* Problem statement (Eq. 1-3; parameter names as in the paper's provenance
+ * record, Listing 1). */
+typedef struct gs_params {
+    int32_t nx, ny, nz;   /* grid; each >= 4, nx % 8 == 0 (else GS_ERR_UNSUPPORTED) */
+    int32_t storage;      /* gs_dtype */
+    double Du, Dv;        /* diffusion rates, finite, >= 0 */
+    double F, k;          /* feed and kill rates, finite */
+    double dt;            /* time step, finite */
+    double noise;         /* magnitude n of the noise term n r on U; finite, >= 0; 0 disables it */
+    uint64_t seed;        /* Philox4x32-10 key for r */
+    uint64_t step0;       /* global index of the initial state's step (resume) */
+    int32_t init_mode;    /* gs_init_mode */
+    int32_t cube_side;    /* GS_INIT_CUBE only: 1 <= cube_side <= min(nx, ny, nz) */
+    double cube_u, cube_v;
+    int32_t tblock;       /* time steps fused per sweep: 0 = library choice, else 1..GS_MAX_TBLOCK */
+    int32_t tile;         /* tile shape index: 0 = library choice, else 1..gs_num_tiles() */
+} gs_params;
+
+#define GS_MAX_TBLOCK 4
+
+/* The noise r(seed, t, idx) of step t (0-based index of the step being taken,
+ * i.e. step0 + steps already done) at cell idx is word (idx % 4) of the
+ * Philox4x32-10 block with counter (low, high halves of idx / 4, low, high
+ * halves of t) and key (low, high halves of seed), read as a signed 32-bit
+ * integer w and mapped to (w + 0.5) * 2^-31, an exact FP64 value in (-1, 1).
+ * It is added to U's bracket in Eq. 2a, i.e. multiplied by dt. */
+
+typedef struct gs_sim gs_sim; /* opaque handle */
+
+typedef struct gs_diag {
+    double sum_u, sum_v;      /* compensated FP64 sums over all cells */
+    double min_u, max_u, min_v, max_v; /* over the finite cells */
+    int64_t nonfinite;        /* number of NaN or Inf values in u and v together */
+} gs_diag;
+
+/* Library version string (static storage). */
+const char *gs_version(void);
+
+/* Thread-local message describing the last failed call on this thread. */
+const char *gs_last_error(void);
+
+/* Bytes of device workspace gs_init needs for this problem (diagnostic
+ * partials); 0 for invalid params. The caller allocates it. */
+size_t gs_workspace_bytes(const gs_params *p);
+
+/* Number of tile shapes the step kernels offer (valid gs_params.tile values
+ * are 1..gs_num_tiles()) and their description. */
+int32_t gs_num_tiles(void);
+gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t *tx, int32_t *ty, int32_t *zc);
+
+/* Binds four caller-owned device buffers of nx*ny*nz elements of the storage
+ * type. (u0, v0) hold the state at step p->step0; (u1, v1) receive the next
+ * level; the library ping-pongs between the pairs. `workspace` holds
+ * gs_workspace_bytes(p) bytes. If p->init_mode == GS_INIT_CUBE the init
+ * kernel fills (u0, v0) on `hip_stream`. Does not allocate device memory.
+ * On success *out is a new handle; on failure *out is NULL. */
+gs_status gs_init(const gs_params *p, void *u0, void *v0, void *u1, void *v1,
+                  void *workspace, void *hip_stream, gs_sim **out);
+
+/* Advances the state by n_steps >= 0 steps (Eq. 2a/2b), enqueued on the
+ * handle's stream; returns after the launches. n_steps == 0 is a no-op.
+ * Launch failures return GS_ERR_HIP; faults inside kernels surface at the
+ * next synchronising call. */
+gs_status gs_step(gs_sim *s, int64_t n_steps);
+
+/* Synchronising. Copies the current u and/or v, widened to FP64, into host
+ * arrays of nx*ny*nz doubles (NULL skips that field). */
+gs_status gs_read(gs_sim *s, double *u_host, double *v_host);
+
+/* Synchronising. Replaces the current u and/or v by host FP64 arrays of
+ * nx*ny*nz doubles, rounded to the storage type (to FP32 first, then to the
+ * 16-bit type; nearest-even). NULL leaves that field unchanged. */
+gs_status gs_write(gs_sim *s, const double *u_host, const double *v_host);
+
+/* Zero-copy view: device pointers of the buffers holding the current state,
+ * and the global step index of that state. Any output pointer may be NULL. */
+gs_status gs_current(gs_sim *s, void **u_dev, void **v_dev, uint64_t *step);
+
+/* Synchronising. FP64 compensated sums (the mass sum(u + v) is
+ * sum_u + sum_v), per-field min/max and the non-finite count of the current
+ * state. Returns GS_ERR_NONFINITE (with *out filled) when nonfinite > 0. */
+gs_status gs_diagnostics(gs_sim *s, gs_diag *out);
+
+/* Waits for all work enqueued by this handle. */
+gs_status gs_sync(gs_sim *s);
+
+/* Frees the handle only (not the caller's buffers); waits for its work first.
+ * Any later call with this handle returns GS_ERR_STATE. */
+gs_status gs_destroy(gs_sim *s);
+
+/* ------------------------------------------------------------------ */
+/* Calibration kernels (measure the single-field stencil and plain streaming
+ * on the same device, the analogue of the paper's Table 2 / Table 3 rows). */
+
+/* Single-field FP64 7-point periodic Laplacian (Eq. 3): out = (sum of six
+ * neighbours - 6 f) / 6, bitwise equal to the IEEE division. f and out are
+ * device arrays of nx*ny*nz doubles (must not overlap); nx % 8 == 0. */
+gs_status gs_laplacian7(const double *f, double *out, int32_t nx, int32_t ny, int32_t nz,
+                        void *hip_stream);
+
+/* Plain device-to-device copy of `bytes` bytes (multiple of 16) with the
+ * library's own streaming kernel: the achievable-bandwidth reference. */
+gs_status gs_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -187,5 +187,58 @@ int gso_run(int nx, int ny, int nz, double Du, double Dv, double F, double k,
     return 0;
 }
 
+/* The same steps evaluated on a w*w*w window of a larger periodic grid
+ * (nx, ny, nz), for checking sampled cells of large runs one by one. Window
+ * cell (i, j, l) is global cell ((x0 + i) mod nx, (y0 + j) mod ny,
+ * (z0 + l) mod nz), and the noise is keyed by the global index. Step s
+ * (s = 0, 1, ...) recomputes only cells at least s + 1 cells from the
+ * window's faces, whose six neighbours are all still exact; after n_steps
+ * the cells at least n_steps from every face hold the exact values.
+ * u, v: w^3 doubles each, x fastest, updated in place. Returns 0, or -1 if
+ * scratch memory could not be allocated.                                  */
+int gso_run_window(int nx, int ny, int nz, int x0, int y0, int z0, int w,
+                   double Du, double Dv, double F, double k, double dt, double noise,
+                   uint64_t seed, uint64_t step0, int64_t n_steps, double *u, double *v)
+{
+    size_t n = (size_t)w * (size_t)w * (size_t)w;
+    double *nu = (double *)malloc(n * sizeof(double));
+    double *nv = (double *)malloc(n * sizeof(double));
+    if (!nu || !nv) { free(nu); free(nv); return -1; }
+#define W(A, I, J, L) A[(size_t)(I) + (size_t)w * ((size_t)(J) + (size_t)w * (size_t)(L))]
+    for (int64_t s = 0; s < n_steps; ++s) {
+        int lo = (int)s + 1, hi = w - (int)s - 1;
+        memcpy(nu, u, n * sizeof(double));
+        memcpy(nv, v, n * sizeof(double));
+        for (int l = lo; l < hi; ++l)
+            for (int j = lo; j < hi; ++j)
+                for (int i = lo; i < hi; ++i) {
+                    double uc = W(u, i, j, l), vc = W(v, i, j, l);
+                    double su = ((W(u, i - 1, j, l) + W(u, i + 1, j, l)) + (W(u, i, j - 1, l) + W(u, i, j + 1, l)))
+                                + (W(u, i, j, l - 1) + W(u, i, j, l + 1));
+                    double sv = ((W(v, i - 1, j, l) + W(v, i + 1, j, l)) + (W(v, i, j - 1, l) + W(v, i, j + 1, l)))
+                                + (W(v, i, j, l - 1) + W(v, i, j, l + 1));
+                    double lapu = (su - 6.0 * uc) / 6.0;
+                    double lapv = (sv - 6.0 * vc) / 6.0;
+                    double uvv = uc * (vc * vc);
+                    double du = (Du * lapu - uvv) + F * (1.0 - uc);
+                    if (noise != 0.0) {
+                        int gx = ((x0 + i) % nx + nx) % nx;
+                        int gy = ((y0 + j) % ny + ny) % ny;
+                        int gz = ((z0 + l) % nz + nz) % nz;
+                        uint64_t idx = (uint64_t)gx + (uint64_t)nx * ((uint64_t)gy + (uint64_t)ny * (uint64_t)gz);
+                        du = du + noise * gso_noise_r(seed, step0 + (uint64_t)s, idx);
+                    }
+                    double dv = (Dv * lapv + uvv) - (F + k) * vc;
+                    W(nu, i, j, l) = uc + du * dt;
+                    W(nv, i, j, l) = vc + dv * dt;
+                }
+        memcpy(u, nu, n * sizeof(double));
+        memcpy(v, nv, n * sizeof(double));
+    }
+#undef W
+    free(nu); free(nv);
+    return 0;
+}
+
 void gso_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 int gso_max_threads(void) { return omp_get_max_threads(); }

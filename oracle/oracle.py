@@ -48,6 +48,7 @@ class OracleLib:
             "gso_laplacian": ([i, i, i, dp, dp], None),
             "gso_step": ([i, i, i, d, d, d, d, d, d, u64, u64, dp, dp, dp, dp], None),
             "gso_run": ([i, i, i, d, d, d, d, d, d, u64, u64, i64, dp, dp], ctypes.c_int),
+            "gso_run_window": ([i, i, i, i, i, i, i, d, d, d, d, d, d, u64, u64, i64, dp, dp], ctypes.c_int),
             "gso_set_threads": ([i], None),
             "gso_max_threads": ([], i),
         }
@@ -150,6 +151,32 @@ def run(u, v, n_steps, *, Du, Dv, F, k, dt, noise=0.0, seed=0, step0=0, impl=Non
     if rc != 0:
         raise MemoryError("oracle scratch allocation failed")
     return u, v
+
+
+def extract_window(f: np.ndarray, x0: int, y0: int, z0: int, w: int) -> np.ndarray:
+    """w^3 periodic window of a (nz, ny, nx) field with lower corner (x0, y0, z0)."""
+    nz, ny, nx = f.shape
+    zi = (z0 + np.arange(w)) % nz
+    yi = (y0 + np.arange(w)) % ny
+    xi = (x0 + np.arange(w)) % nx
+    return np.ascontiguousarray(f[np.ix_(zi, yi, xi)])
+
+
+def run_window(uw, vw, grid_shape, corner, n_steps, *, Du, Dv, F, k, dt, noise=0.0, seed=0, step0=0,
+               impl=None, **_ignored):
+    """Advance a w^3 window (see gso_run_window); returns new (u, v) windows
+    whose cells at least n_steps from every face are exact."""
+    uw = np.array(uw, dtype=np.float64, order="C", copy=True)
+    vw = np.array(vw, dtype=np.float64, order="C", copy=True)
+    w = uw.shape[0]
+    assert uw.shape == (w, w, w) == vw.shape
+    nz, ny, nx = grid_shape
+    x0, y0, z0 = corner
+    rc = lib(impl).gso_run_window(nx, ny, nz, x0, y0, z0, w, Du, Dv, F, k, dt, noise, seed, step0,
+                                  int(n_steps), _dp(uw), _dp(vw))
+    if rc != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return uw, vw
 
 
 def diagnostics(u: np.ndarray, v: np.ndarray) -> dict:

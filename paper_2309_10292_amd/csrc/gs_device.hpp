@@ -1,0 +1,175 @@
+// Device-side building blocks of the Gray-Scott kernels for gfx950:
+// storage-type conversion, Philox4x32-10 noise, FP64 division by 6, the
+// compensated FP32 Laplacian, and a z-streaming tile of one field (global ->
+// registers -> LDS) shared by the step and Laplacian kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+// ---------------------------------------------------------------- storage
+struct bf16 {
+    uint16_t bits;
+};
+typedef _Float16 f16;
+
+__device__ __forceinline__ float to_f32(float x) { return x; }
+__device__ __forceinline__ float to_f32(f16 x) { return (float)x; }
+__device__ __forceinline__ float to_f32(bf16 x) { return __uint_as_float((uint32_t)x.bits << 16); }
+
+// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
+__device__ __forceinline__ bf16 bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    bf16 r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r.bits = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+}
+
+// Compute type C and conversions for each storage type S.
+template <typename S> struct Traits;
+template <> struct Traits<double> {
+    typedef double C;
+    static __device__ __forceinline__ double load(double s) { return s; }
+    static __device__ __forceinline__ double store(double c) { return c; }
+};
+template <> struct Traits<float> {
+    typedef float C;
+    static __device__ __forceinline__ float load(float s) { return s; }
+    static __device__ __forceinline__ float store(float c) { return c; }
+};
+template <> struct Traits<bf16> {
+    typedef float C;
+    static __device__ __forceinline__ float load(bf16 s) { return to_f32(s); }
+    static __device__ __forceinline__ bf16 store(float c) { return bf16_rne(c); }
+};
+template <> struct Traits<f16> {
+    typedef float C;
+    static __device__ __forceinline__ float load(f16 s) { return (float)s; }
+    static __device__ __forceinline__ f16 store(float c) { return (f16)c; }
+};
+
+// V consecutive storage elements moved as one aligned vector access.
+template <typename S, int V> struct alignas(16) Vec {
+    S e[V];
+};
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds; each multiplies counter
+// words 0 and 2 by the round multipliers into 64-bit products and recombines
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is
+// advanced by the two Weyl increments between rounds. The key and the step
+// words are uniform across the launch.
+struct Philox4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_lo = 0xD2511F53u * c0;
+        const uint32_t a_hi = __umulhi(0xD2511F53u, c0);
+        const uint32_t b_lo = 0xCD9E8D57u * c2;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c2);
+        c0 = b_hi ^ c1 ^ k0;
+        c1 = b_lo;
+        c2 = a_hi ^ c3 ^ k1;
+        c3 = a_lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 o;
+    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+    return o;
+}
+
+// r = (w + 1/2) 2^-31 for the signed word w: exact in FP64, in (-1, 1).
+__device__ __forceinline__ double noise_word_f64(uint32_t w)
+{
+    return ((double)(int32_t)w + 0.5) * 0x1p-31;
+}
+__device__ __forceinline__ float noise_word_f32(uint32_t w)
+{
+    return (float)(((double)(int32_t)w + 0.5) * 0x1p-31);
+}
+
+// Noise of the 4 cells idx4 .. idx4+3 (idx4 a multiple of 4) at step t.
+__device__ __forceinline__ Philox4 noise_block(uint64_t idx4, uint64_t t, uint64_t seed)
+{
+    const uint64_t q = idx4 >> 2;
+    return philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), (uint32_t)t, (uint32_t)(t >> 32),
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// ---------------------------------------------------------------- arithmetic
+// Correctly rounded x / 6 without the FP64 divide sequence. With h = RN(1/6)
+// and q0 = RN(x h), the residual r = x - 6 q0 is a small multiple of ulp(q0)
+// and so exact in one fma, and RN(q0 + r h) == RN(x / 6): x / 6 = m ulp(x) / 6
+// for an integer m, and such a value is never closer than ulp(x) / 48 to a
+// rounding boundary of the result (odd multiples of ulp(x) / 16 or / 8, which
+// would need m divisible by 3 and an even multiplier at once), whereas
+// q0 + r h - x / 6 = r (h - 1/6) is below 2 ulp(x) * 2^-56. Valid for x in
+// the normal range away from overflow, which covers the Laplacian's argument.
+__device__ __forceinline__ double div6(double x)
+{
+    const double h = 1.0 / 6.0;
+    const double q0 = x * h;
+    const double r = __builtin_fma(-q0, 6.0, x);
+    return __builtin_fma(r, h, q0);
+}
+
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Laplacian in FP32 from the differences d_i = n_i - c (exact when a
+// neighbour is within a factor 2 of c), summed with TwoSum compensation.
+__device__ __forceinline__ float lap_comp_f32(float c, float xm, float xp, float ym, float yp,
+                                              float zm, float zp)
+{
+    float s, e, t, err;
+    two_sum(xm - c, xp - c, s, e);
+    two_sum(s, ym - c, t, err); s = t; e += err;
+    two_sum(s, yp - c, t, err); s = t; e += err;
+    two_sum(s, zm - c, t, err); s = t; e += err;
+    two_sum(s, zp - c, t, err); s = t; e += err;
+    return (s + e) * (1.0f / 6.0f);
+}
+
+// FP64 Laplacian in the canonical order: ((x- + x+) + (y- + y+)) + (z- + z+),
+// then (sum - 6 c) / 6.
+__device__ __forceinline__ double lap_f64(double c, double xm, double xp, double ym, double yp,
+                                          double zm, double zp)
+{
+    const double s = ((xm + xp) + (ym + yp)) + (zm + zp);
+    const double c6 = 6.0 * c;
+    return div6(s - c6);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Block index -> logical tile index such that the blocks the dispatcher
+// sends to one XCD (hardware block ids congruent mod 8) get one contiguous
+// range of logical tiles, so halos and z-chunk edges are shared in that
+// XCD's L2.
+__device__ __forceinline__ uint32_t xcd_logical_block(uint32_t b, uint32_t nb)
+{
+    const uint32_t per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7u) * per + (b >> 3);
+}
+
+} // namespace gs

@@ -1,0 +1,65 @@
+// Internal interface between the C ABI (gs_api.cpp) and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gs {
+
+// Everything a step launch needs, by value (kernel argument).
+struct StepArgs {
+    int nx, ny, nz;
+    int zc;              // planes per z-chunk
+    int ntx, nty;        // tiles per row / column (set by the launcher)
+    double Du, Dv, F, FK, dt, noise;   // FK = F + k, rounded once
+    float Du_f, Dv_f, F_f, FK_f, dt_f, noise_f;
+    uint64_t seed;
+    uint64_t t;          // global index of the step being taken (noise key)
+};
+
+template <typename C> struct Coef;
+template <> struct Coef<double> {
+    static __host__ __device__ double Du(const StepArgs &a) { return a.Du; }
+    static __host__ __device__ double Dv(const StepArgs &a) { return a.Dv; }
+    static __host__ __device__ double F(const StepArgs &a) { return a.F; }
+    static __host__ __device__ double FK(const StepArgs &a) { return a.FK; }
+    static __host__ __device__ double dt(const StepArgs &a) { return a.dt; }
+    static __host__ __device__ double noise(const StepArgs &a) { return a.noise; }
+};
+template <> struct Coef<float> {
+    static __host__ __device__ float Du(const StepArgs &a) { return a.Du_f; }
+    static __host__ __device__ float Dv(const StepArgs &a) { return a.Dv_f; }
+    static __host__ __device__ float F(const StepArgs &a) { return a.F_f; }
+    static __host__ __device__ float FK(const StepArgs &a) { return a.FK_f; }
+    static __host__ __device__ float dt(const StepArgs &a) { return a.dt_f; }
+    static __host__ __device__ float noise(const StepArgs &a) { return a.noise_f; }
+};
+
+struct TileShape {
+    int tx, ty;
+};
+
+int num_tiles();
+TileShape tile_shape(int tile, int storage);
+
+// One step (u, v) -> (un, vn) with the given tile (1..num_tiles()).
+hipError_t launch_step(int storage, int tile, const void *u, const void *v, void *un, void *vn,
+                       const StepArgs &a, hipStream_t st);
+
+hipError_t launch_laplacian7(const double *f, double *out, int nx, int ny, int nz, hipStream_t st);
+
+// Cube initial state in the storage type.
+hipError_t launch_init_cube(int storage, void *u, void *v, int nx, int ny, int nz, int side,
+                            double cu, double cv, hipStream_t st);
+
+// Diagnostics: per-block partials into `ws`, then one block folds them.
+// Result (9 doubles: sum_u, comp_u, sum_v, comp_v, min_u, max_u, min_v,
+// max_v, nonfinite as double) lands at ws + diag_result_offset().
+hipError_t launch_diagnostics(int storage, const void *u, const void *v, size_t n, void *ws, hipStream_t st);
+size_t diag_workspace_bytes();
+size_t diag_result_offset();
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+
+} // namespace gs

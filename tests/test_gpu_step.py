@@ -1,0 +1,250 @@
+"""GPU parity of the fused step (libgs through its C ABI) against the FP64
+oracle. FP64 storage must match bit for bit (the contract is max-abs 1e-12
+after 100 steps; the kernels follow the oracle's operation order, so the
+expected difference is exactly zero)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import random_state, workload
+from tests.gpu_util import max_abs, require_gpu, window_from_device
+
+pytestmark = pytest.mark.gpu
+
+P0 = {k: workload("small_l64")[k] for k in ("Du", "Dv", "F", "k", "dt")}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def small_ref():
+    p = workload("small_l64")
+    u0, v0 = O.init_cube(L=p["L"], side=p["cube_side"], cu=p["cube_u"], cv=p["cube_v"])
+    return O.run(u0, v0, p["steps"], **p)
+
+
+def _sim(shape, **kw):
+    from paper_2309_10292_amd import gs
+    nz, ny, nx = shape
+    return gs.Sim(nx, ny, nz, **kw)
+
+
+def test_init_cube_matches_oracle(torch):
+    for storage in ("f64",):
+        with _sim((64, 64, 64), storage=storage, cube_side=12) as s:
+            u, v = s.read()
+        ue, ve = O.init_cube(L=64, side=12)
+        assert np.array_equal(u, ue) and np.array_equal(v, ve)
+    with _sim((20, 16, 24), cube_side=5, cube_u=0.4, cube_v=0.2) as s:
+        u, v = s.read()
+    ue, ve = O.init_cube(shape=(20, 16, 24), side=5, cu=0.4, cv=0.2)
+    assert np.array_equal(u, ue) and np.array_equal(v, ve)
+
+
+def test_small_l64_fp64_bitwise(torch, small_ref):
+    p = workload("small_l64")
+    from paper_2309_10292_amd import gs
+    L = gs.load()
+    for tile in range(0, L.gs_num_tiles() + 1):
+        with _sim((64, 64, 64), storage="f64", tile=tile, **P0) as s:
+            s.step(p["steps"])
+            u, v = s.read()
+        err = max(max_abs(u, small_ref[0]), max_abs(v, small_ref[1]))
+        assert err <= 1e-12, f"tile {tile}: max-abs {err}"
+        assert np.array_equal(u, small_ref[0]) and np.array_equal(v, small_ref[1]), f"tile {tile} not bitwise"
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 8), (20, 36, 40), (9, 13, 24), (6, 20, 136), (70, 5, 16)])
+def test_ragged_shapes_with_noise_bitwise(torch, shape):
+    from paper_2309_10292_amd import gs
+    u0, v0 = random_state(shape, seed=sum(shape), lo_u=0.2, hi_u=1.0, lo_v=0.0, hi_v=0.5)
+    p = dict(Du=0.19, Dv=0.11, F=0.029, k=0.055, dt=0.9, noise=0.01, seed=31337, step0=123)
+    ue, ve = O.run(u0, v0, 5, **p)
+    for tile in range(1, gs.load().gs_num_tiles() + 1):
+        with _sim(shape, u0=u0, v0=v0, tile=tile, **p) as s:
+            s.step(5)
+            u, v = s.read()
+        assert np.array_equal(u, ue) and np.array_equal(v, ve), f"shape {shape} tile {tile}: {max_abs(u, ue)}"
+
+
+def test_noise_config_bitwise(torch):
+    """The noisy workload's parameters (noise 1e-7) and a stronger noise on an
+    L=64 grid from the cube state, 40 steps."""
+    for noise in (1e-7, 0.05):
+        p = dict(workload("weak_share_l512"))
+        p.update(noise=noise)
+        u0, v0 = O.init_cube(L=64)
+        ue, ve = O.run(u0, v0, 40, **p)
+        with _sim((64, 64, 64), **{k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}) as s:
+            s.step(40)
+            u, v = s.read()
+        assert np.array_equal(u, ue) and np.array_equal(v, ve), (noise, max_abs(u, ue))
+
+
+def test_resume_bitwise(torch):
+    p = dict(P0, noise=0.02, seed=99)
+    with _sim((32, 32, 32), cube_side=10, **p) as s:
+        s.step(30)
+        u_full, v_full = s.read()
+    with _sim((32, 32, 32), cube_side=10, **p) as s:
+        s.step(15)
+        u_mid, v_mid = s.read()
+        _, _, st = s.current()
+        assert st == 15
+    with _sim((32, 32, 32), u0=u_mid, v0=v_mid, step0=15, **p) as s:
+        s.step(15)
+        u2, v2 = s.read()
+    assert np.array_equal(u_full, u2) and np.array_equal(v_full, v2)
+
+
+def test_step_zero_and_split_calls(torch):
+    """gs_step(0) is a no-op; gs_step(a) + gs_step(b) == gs_step(a + b)."""
+    with _sim((24, 24, 32), noise=1e-3, seed=5, **P0) as s:
+        s.step(0)
+        s.step(3)
+        s.step(4)
+        a = s.read()
+    with _sim((24, 24, 32), noise=1e-3, seed=5, **P0) as s:
+        s.step(7)
+        b = s.read()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_deterministic_repeat(torch):
+    """Two runs give the same bits (a race in LDS staging would show here)."""
+    outs = []
+    for _ in range(2):
+        with _sim((64, 96, 128), noise=1e-4, seed=3, cube_side=30, **P0) as s:
+            s.step(25)
+            outs.append(s.read())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_fixed_point_all_storage_types(torch):
+    for storage in ("f64", "f32", "bf16", "f16"):
+        with _sim((16, 16, 16), storage=storage, cube_side=1, cube_u=1.0, cube_v=0.0, **P0) as s:
+            s.step(10)
+            u, v = s.read()
+        assert np.all(u == 1.0) and np.all(v == 0.0), storage
+
+
+def test_diagnostics_vs_oracle(torch, small_ref):
+    p = workload("small_l64")
+    with _sim((64, 64, 64), **P0) as s:
+        s.step(p["steps"])
+        d = s.diagnostics()
+        u_t, v_t, _ = s.current()
+        e = O.diagnostics(*small_ref)
+        for key in ("sum_u", "sum_v"):
+            assert abs(d[key] - e[key]) <= 1e-14 * abs(e[key]), key
+        for key in ("min_u", "max_u", "min_v", "max_v"):
+            assert d[key] == e[key], key
+        assert d["nonfinite"] == 0
+        # a non-finite value written by the caller is counted and reported
+        u_t.view(-1)[12345] = float("nan")
+        v_t.view(-1)[7] = float("inf")
+        torch.cuda.synchronize()
+        from paper_2309_10292_amd import gs
+        with pytest.raises(gs.GSError) as ei:
+            s.diagnostics()
+        assert ei.value.status == gs.GS_ERR_NONFINITE
+        d2 = s.diagnostics(allow_nonfinite=True)
+        assert d2["nonfinite"] == 2
+
+
+def test_reduced_precision_within_bars(torch, small_ref):
+    """FP32 / FP16 / BF16 storage (FP32 arithmetic, compensated Laplacian) on
+    the L=64 workload, 100 steps, against the FP64 oracle."""
+    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}
+    p = workload("small_l64")
+    for storage, bar in bars.items():
+        with _sim((64, 64, 64), storage=storage, **P0) as s:
+            s.step(p["steps"])
+            u, v = s.read()
+        err = max(max_abs(u, small_ref[0]), max_abs(v, small_ref[1]))
+        print(f"{storage}: max-abs {err:.3e}")
+        assert err <= bar, (storage, err)
+
+
+def test_laplacian7_bitwise(torch):
+    from paper_2309_10292_amd import gs
+    for shape in [(24, 40, 64), (5, 7, 16), (33, 17, 200)]:
+        f = np.random.default_rng(len(shape)).uniform(-1, 1, size=shape)
+        ft = torch.from_numpy(f).cuda()
+        out = gs.laplacian7(ft)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), O.laplacian(f)), shape
+
+
+def test_copy_kernel(torch):
+    from paper_2309_10292_amd import gs
+    a = torch.randint(0, 255, (1 << 20,), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    gs.copy(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def _sampled_windows(s_state_prev, s_state_now, shape, p, step_prev, n, corners, w=16):
+    (up, vp), (un, vn) = s_state_prev, s_state_now
+    p = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
+    for corner in corners:
+        uw = window_from_device(up, *corner, w)
+        vw = window_from_device(vp, *corner, w)
+        ue, ve = O.run_window(uw, vw, shape, corner, n, step0=step_prev, **p)
+        inner = slice(n, w - n)
+        ug = window_from_device(un, *corner, w)[inner, inner, inner]
+        vg = window_from_device(vn, *corner, w)[inner, inner, inner]
+        assert np.array_equal(ug, ue[inner, inner, inner]), (corner, max_abs(ug, ue[inner, inner, inner]))
+        assert np.array_equal(vg, ve[inner, inner, inner]), corner
+
+
+def test_full_size_l512_noise(torch):
+    """One GPU's weak-scaling share, L=512, noise 1e-7, 1000 steps, in the
+    launch configuration the benchmark times: the first two steps are
+    compared over the whole field, the last five on sampled windows (cells
+    evaluated one by one by the oracle from the GPU's own state at step 995,
+    covering the cube's centre, its edge, quiet cells and the periodic seam)."""
+    p = workload("weak_share_l512")
+    L = p["L"]
+    shape = (L, L, L)
+    kw = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
+    with _sim(shape, **kw) as s:
+        s.step(2)
+        u, v = s.read()
+        u0, v0 = O.init_cube(L=L)
+        ue, ve = O.run(u0, v0, 2, **p)
+        assert np.array_equal(u, ue) and np.array_equal(v, ve), max_abs(u, ue)
+        del u, v, ue, ve, u0, v0
+        s.step(p["steps"] - 2 - 5)
+        u_t, v_t, st = s.current()
+        assert st == p["steps"] - 5
+        prev = (u_t.clone(), v_t.clone())
+        s.step(5)
+        u_t, v_t, st = s.current()
+        assert st == p["steps"]
+        corners = [(248, 248, 248), (240, 250, 260), (0, 0, 0), (505, 505, 505), (100, 300, 200), (500, 3, 255)]
+        _sampled_windows(prev, (u_t, v_t), shape, dict(p), p["steps"] - 5, 5, corners)
+
+
+def test_full_size_l1024_fp64_sampled(torch):
+    """The L=1024 precision workload in FP64 (F=0.03, k=0.06, 200 steps):
+    sampled windows for the last four steps against the oracle."""
+    p = workload("precision_l1024")
+    L = p["L"]
+    shape = (L, L, L)
+    kw = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise")}
+    with _sim(shape, **kw) as s:
+        s.step(p["steps"] - 4)
+        u_t, v_t, _ = s.current()
+        prev = (u_t.clone(), v_t.clone())
+        s.step(4)
+        u_t, v_t, st = s.current()
+        assert st == p["steps"]
+        c = (L - 12) // 2
+        corners = [(c, c, c), (c - 8, c + 4, c - 2), (c + 10, c - 10, c + 5), (0, 0, 0), (1016, 1016, 1016)]
+        _sampled_windows(prev, (u_t, v_t), shape, dict(p), p["steps"] - 4, 4, corners)
+        del prev
