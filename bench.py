@@ -35,8 +35,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f64", choices=list(BYTES_PER_CELL))
     ap.add_argument("--L", type=int, default=512)
-    ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--variants", default="f32,bf16,f16", help="other storage types to time ('' for none)")
+    ap.add_argument("--tile", type=int, default=0, help="0 = library choice")
+    ap.add_argument("--tblock", type=int, default=0, help="fused steps per sweep, 0 = library choice")
+    ap.add_argument("--zchunk", type=int, default=0, help="planes per workgroup chunk, 0 = library choice")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch configuration first")
+XX
     ap.add_argument("--variant-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
@@ -45,19 +48,27 @@ def parse():
 
 
 def time_steps(torch, sim, steps, warmup):
-    """Average per-launch time (ms) of `steps` step launches, HIP events on the
-    stream the library launches on (torch's current stream, bound at init)."""
+    """Times `steps` steps with HIP events on the stream the library launches
+    on (torch's current stream, bound at init). Returns (ms per step, ms per
+    launch of the full-depth sweeps, launches timed)."""
+    cfg = sim.config()
+    T = cfg["tblock"]
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    sim.step(steps)
-    e1.record(st)
-    e1.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    full = (steps // T) * T
+    ev[0].record(st)
+    sim.step(full)
+    ev[1].record(st)
+    sim.step(steps - full)
+    ev[2].record(st)
+    ev[2].synchronize()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    total = ev[0].elapsed_time(ev[2])
+    per_launch = ev[0].elapsed_time(ev[1]) / max(1, full // T)
+    return total / steps, per_launch, full // T
 
 
 def traffic_for(path, kernel_key):
@@ -101,29 +112,39 @@ def main():
     L = a.L
     p = {k: wl[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
 
-    def measure(storage, steps, warmup):
-        with gs.Sim(L, L, L, storage=storage, tile=a.tile, cube_side=wl["cube_side"], **p) as s:
-            ms = time_steps(torch, s, steps, warmup)
+    def measure(storage, steps, warmup, main=False):
+        kw = dict(tile=a.tile, tblock=a.tblock, zchunk=a.zchunk) if main else {}
+        with gs.Sim(L, L, L, storage=storage, cube_side=wl["cube_side"], **kw, **p) as s:
+            if main and a.tune:
+                s.tune(reps=2)
+            cfg = s.config()
+            ms, per_launch, launches = time_steps(torch, s, steps, warmup)
             d = s.diagnostics(allow_nonfinite=True)
-        return ms, d
+        return ms, per_launch, launches, cfg, d
 
-    ms, diag = measure(a.storage, a.steps, a.warmup)
+    ms, per_launch, launches, cfg, diag = measure(a.storage, a.steps, a.warmup, main=True)
     cells = L ** 3
     value = cells / (ms * 1e-3) / 1e9
     bpc = BYTES_PER_CELL[a.storage]
-    achieved = bpc * cells / (ms * 1e-3) / 1e9
-    kernel_key = f"step_{a.storage}_L{L}"
+    T = cfg["tblock"]
+    # Algorithmic HBM bytes of one launch: both fields read once and written
+    # once, whatever the number of fused steps.
+    achieved = bpc * cells / (per_launch * 1e-3) / 1e9
+    kname = "stencil_tb" if cfg["tile"] > 4 else "stencil_tile"
+    kernel_key = f"{kname}_{a.storage}_T{T}_L{L}"
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_for(a.traffic_file, kernel_key),
-                kernel="stencil_tile (fused step)", bytes_per_cell=bpc, launches=a.steps)
+                kernel=f"{kname} ({T} fused steps per launch)", bytes_per_cell_per_launch=bpc,
+                launches_timed=launches, ms_per_launch=round(per_launch, 5),
+                single_step_equivalent_gbs=round(bpc * cells / (ms * 1e-3) / 1e9, 1))
 
     variants = {}
-    for sv in [x for x in a.variants.split(",") if x and x != a.storage]:
-        vms, vd = measure(sv, a.variant_steps, a.warmup)
+    for sv in [x for x in a.variants.split(",") if x and x not in (a.storage, "none")]:
+        vms, _, _, vcfg, vd = measure(sv, a.variant_steps, a.warmup)
         vach = BYTES_PER_CELL[sv] * cells / (vms * 1e-3) / 1e9
         variants[sv] = dict(value=round(cells / (vms * 1e-3) / 1e9, 3), ms_per_step=round(vms, 5),
-                            hbm_gbs=round(vach, 1), frac=round(vach / HBM_PEAK_GBS, 4), steps=a.variant_steps,
-                            bytes_per_cell=BYTES_PER_CELL[sv])
+                            single_step_equivalent_gbs=round(vach, 1), steps=a.variant_steps,
+                            bytes_per_cell=BYTES_PER_CELL[sv], launch_config=vcfg)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -144,7 +165,7 @@ def main():
         "data": "synthetic (cube initial state, Philox noise)",
         "config": {"workload": f"gray-scott periodic {L}^3, noise 1e-7, {a.storage} storage (one GPU's weak-scaling share)",
                    "L": L, "Du": p["Du"], "Dv": p["Dv"], "F": p["F"], "k": p["k"], "dt": p["dt"],
-                   "noise": p["noise"], "tile": a.tile},
+                   "noise": p["noise"], "launch": cfg},
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,

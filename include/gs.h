@@ -71,6 +71,8 @@ typedef struct gs_params {
     double cube_u, cube_v;
     int32_t tblock;       /* time steps fused per sweep: 0 = library choice, else 1..GS_MAX_TBLOCK */
     int32_t tile;         /* tile shape index: 0 = library choice, else 1..gs_num_tiles() */
+    int32_t zchunk;       /* planes per z-chunk of one workgroup: 0 = library choice, else >= 1 */
+    int32_t reserved;     /* must be 0 */
 } gs_params;
 
 #define GS_MAX_TBLOCK 4
@@ -97,13 +99,18 @@ const char *gs_version(void);
 const char *gs_last_error(void);
 
 /* Bytes of device workspace gs_init needs for this problem (diagnostic
- * partials); 0 for invalid params. The caller allocates it. */
+ * partials and the graph-replay step counter); 0 for invalid params. The
+ * caller allocates it. */
 size_t gs_workspace_bytes(const gs_params *p);
 
-/* Number of tile shapes the step kernels offer (valid gs_params.tile values
- * are 1..gs_num_tiles()) and their description. */
+/* Tile shapes (valid gs_params.tile values are 1..gs_num_tiles()). The first
+ * four select the single-step z-streaming kernel (tblock must be 1); the
+ * others select the temporally blocked kernel, which fuses tblock steps per
+ * pass. gs_tile_info reports the output tile (tx cells by ty rows) of `tile`
+ * for a storage type and tblock, and the largest tblock the tile accepts. */
 int32_t gs_num_tiles(void);
-gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t *tx, int32_t *ty, int32_t *zc);
+gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t tblock, int32_t *tx, int32_t *ty,
+                       int32_t *max_tblock);
 
 /* Binds four caller-owned device buffers of nx*ny*nz elements of the storage
  * type. (u0, v0) hold the state at step p->step0; (u1, v1) receive the next
@@ -144,6 +151,35 @@ gs_status gs_sync(gs_sim *s);
 /* Frees the handle only (not the caller's buffers); waits for its work first.
  * Any later call with this handle returns GS_ERR_STATE. */
 gs_status gs_destroy(gs_sim *s);
+
+/* ------------------------------------------------------------------ */
+/* Launch configuration, autotuning and graph replay. */
+
+typedef struct gs_tune_entry {
+    int32_t tile, tblock, zchunk, reserved;
+    double ms_per_step;   /* measured time per time step (ms) */
+} gs_tune_entry;
+
+/* Sets the launch configuration of later steps: tile 1..gs_num_tiles(),
+ * tblock 1..max for that tile (see gs_tile_info), zchunk >= 1 (clamped to nz). */
+gs_status gs_set_config(gs_sim *s, int32_t tile, int32_t tblock, int32_t zchunk);
+gs_status gs_get_config(gs_sim *s, int32_t *tile, int32_t *tblock, int32_t *zchunk);
+
+/* Synchronising autotuner. Times every (tile, tblock, zchunk) candidate with
+ * `reps` >= 1 launches after one warm-up on the handle's own buffers: each
+ * launch reads the current pair and writes the other, so the state and the
+ * step index are unchanged. Selects the fastest (time per step) for later
+ * gs_step / gs_step_graph calls. If `table` is non-NULL the first `capacity`
+ * measurements are written there; *n_entries (if non-NULL) receives the
+ * number of candidates measured. */
+gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacity, int32_t *n_entries);
+
+/* Same result as gs_step(s, n_steps), enqueued as one HIP graph replay. The
+ * graph is captured on first use for this (n_steps, current buffer pair,
+ * configuration) and reused while those stay the same; every replay reads its
+ * start step from a counter in the workspace, set by a one-lane kernel just
+ * before the replay (no memset nodes). */
+gs_status gs_step_graph(gs_sim *s, int64_t n_steps);
 
 /* ------------------------------------------------------------------ */
 /* Calibration kernels (measure the single-field stencil and plain streaming

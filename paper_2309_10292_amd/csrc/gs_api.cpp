@@ -49,6 +49,12 @@ size_t storage_bytes(int32_t s)
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Tile indices: 1..num_tiles() select the single-step z-streaming kernel's
+// shapes; the next num_tb_shapes() indices select the temporally blocked
+// kernel's shapes (any tblock).
+int total_tiles() { return gs::num_tiles() + gs::num_tb_shapes(); }
+bool is_tb_tile(int tile) { return tile > gs::num_tiles(); }
+
 gs_status validate(const gs_params *p)
 {
     if (!p) return fail(GS_ERR_INVALID_ARG, "params is NULL");
@@ -76,8 +82,12 @@ gs_status validate(const gs_params *p)
     }
     if (p->tblock < 0 || p->tblock > GS_MAX_TBLOCK)
         return fail(GS_ERR_INVALID_ARG, "tblock %d outside [0, %d]", p->tblock, GS_MAX_TBLOCK);
-    if (p->tile < 0 || p->tile > gs::num_tiles())
-        return fail(GS_ERR_INVALID_ARG, "tile %d outside [0, %d]", p->tile, gs::num_tiles());
+    if (p->tile < 0 || p->tile > total_tiles())
+        return fail(GS_ERR_INVALID_ARG, "tile %d outside [0, %d]", p->tile, total_tiles());
+    if (p->tile >= 1 && p->tile <= gs::num_tiles() && p->tblock > 1)
+        return fail(GS_ERR_INVALID_ARG, "tile %d is a single-step tile; tblock must be 0 or 1", p->tile);
+    if (p->zchunk < 0) return fail(GS_ERR_INVALID_ARG, "zchunk %d < 0", p->zchunk);
+    if (p->reserved != 0) return fail(GS_ERR_INVALID_ARG, "reserved field must be 0");
     return GS_OK;
 }
 
@@ -101,6 +111,13 @@ float host_from_bf16(uint16_t b)
 
 } // namespace
 
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int64_t n = -1;
+    int parity = -1;
+    int tile = 0, tblock = 0, zc = 0;
+};
+
 struct gs_sim {
     uint32_t magic;
     gs_params p;
@@ -113,6 +130,8 @@ struct gs_sim {
     int zc;
     int tblock;
     size_t n;
+    GraphCache graph;
+    hipStream_t capture_stream;
 };
 
 namespace {
@@ -123,17 +142,30 @@ gs_status check(gs_sim *s)
     return GS_OK;
 }
 
-// Library choice of tile shape and z-chunk (measured on MI355X; see the
-// benchmark's tile sweep).
+// Library choice of the launch configuration before any tuning (from the
+// MI355X sweep at 512^3): large FP64/FP32 grids use the temporally blocked
+// kernel with three fused steps and 128-plane chunks; 16-bit storage is
+// arithmetic-bound and gains nothing from fusing, so it keeps the
+// single-step kernel; small grids keep the single-step kernel with short
+// chunks so that enough workgroups exist.
+bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
+
 int default_tile(const gs_params &p)
 {
-    (void)p;
+    if (large_grid(p) && (p.storage == GS_F64 || p.storage == GS_F32)) return gs::num_tiles() + 2;
     return 1;
 }
 
-int default_zc(const gs_params &p)
+int default_tblock(const gs_params &p, int tile)
 {
-    const int z = 64;
+    if (tile <= gs::num_tiles()) return 1;
+    return (p.storage == GS_F64 || p.storage == GS_F32) ? 3 : 1;
+}
+
+int default_zc(const gs_params &p, int tile)
+{
+    int z = 16;
+    if (large_grid(p)) z = tile > gs::num_tiles() ? 128 : 32;
     return p.nz < z ? p.nz : z;
 }
 
@@ -158,8 +190,50 @@ gs::StepArgs make_args(const gs_sim *s)
     a.noise_f = (float)a.noise;
     a.seed = s->p.seed;
     a.t = s->step;
+    a.t_dev = nullptr;
     return a;
 }
+
+// Enqueues n steps starting from buffer pair *parity on stream st; with
+// t_dev set, kernels read the base step index from device memory and take
+// their offset from it. Leaves the final parity in *parity.
+hipError_t enqueue_steps(gs_sim *s, int64_t n, hipStream_t st, const uint64_t *t_dev, int *parity)
+{
+    int64_t left = n, off = 0;
+    while (left > 0) {
+        gs::StepArgs a = make_args(s);
+        if (t_dev) {
+            a.t = (uint64_t)off;
+            a.t_dev = t_dev;
+        } else {
+            a.t = s->step + (uint64_t)off;
+        }
+        const int q = *parity;
+        hipError_t e;
+        int done = 1;
+        if (is_tb_tile(s->tile)) {
+            done = (int)(left < s->tblock ? left : s->tblock);
+            e = gs::launch_tblock(s->p.storage, done, s->tile - gs::num_tiles(), s->buf[q][0], s->buf[q][1],
+                                  s->buf[q ^ 1][0], s->buf[q ^ 1][1], a, st);
+        } else {
+            e = gs::launch_step(s->p.storage, s->tile, s->buf[q][0], s->buf[q][1], s->buf[q ^ 1][0],
+                                s->buf[q ^ 1][1], a, st);
+        }
+        if (e != hipSuccess) return e;
+        *parity ^= 1;
+        left -= done;
+        off += done;
+    }
+    return hipSuccess;
+}
+
+void drop_graph(gs_sim *s)
+{
+    if (s->graph.exec) hipGraphExecDestroy(s->graph.exec);
+    s->graph = GraphCache();
+}
+
+int tile_max_tblock(int tile) { return is_tb_tile(tile) ? GS_MAX_TBLOCK : 1; }
 
 } // namespace
 
@@ -169,22 +243,28 @@ const char *gs_version(void) { return "gs-mi355x 0.1 (gfx950)"; }
 
 const char *gs_last_error(void) { return g_err.c_str(); }
 
+// Workspace layout: diagnostic partials, then (256-byte aligned) the step
+// counter read by graph replays.
+size_t counter_offset() { return (gs::diag_workspace_bytes() + 255) / 256 * 256; }
+
 size_t gs_workspace_bytes(const gs_params *p)
 {
     if (validate(p) != GS_OK) return 0;
-    return gs::diag_workspace_bytes();
+    return counter_offset() + 256;
 }
 
-int32_t gs_num_tiles(void) { return gs::num_tiles(); }
+int32_t gs_num_tiles(void) { return total_tiles(); }
 
-gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t *tx, int32_t *ty, int32_t *zc)
+gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t tblock, int32_t *tx, int32_t *ty, int32_t *max_tblock)
 {
-    if (tile < 1 || tile > gs::num_tiles()) return fail(GS_ERR_INVALID_ARG, "tile %d out of range", tile);
+    if (tile < 1 || tile > total_tiles()) return fail(GS_ERR_INVALID_ARG, "tile %d out of range", tile);
     if (storage_bytes(storage) == 0) return fail(GS_ERR_INVALID_ARG, "unknown storage type %d", storage);
-    gs::TileShape t = gs::tile_shape(tile, storage);
+    const int mt = is_tb_tile(tile) ? GS_MAX_TBLOCK : 1;
+    if (tblock < 1 || tblock > mt) return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, mt, tile);
+    gs::TileShape t = is_tb_tile(tile) ? gs::tb_shape(tile - gs::num_tiles(), tblock) : gs::tile_shape(tile, storage);
     if (tx) *tx = t.tx;
     if (ty) *ty = t.ty;
-    if (zc) *zc = 64;
+    if (max_tblock) *max_tblock = mt;
     return GS_OK;
 }
 
@@ -219,9 +299,11 @@ gs_status gs_init(const gs_params *p, void *u0, void *v0, void *u1, void *v1, vo
     s->ws = workspace;
     s->stream = (hipStream_t)hip_stream;
     s->tile = p->tile ? p->tile : default_tile(*p);
-    s->zc = default_zc(*p);
-    s->tblock = p->tblock ? p->tblock : 1;
+    s->zc = p->zchunk ? (p->zchunk < p->nz ? p->zchunk : p->nz) : default_zc(*p, s->tile);
+    s->tblock = p->tblock ? p->tblock : default_tblock(*p, s->tile);
     s->n = (size_t)p->nx * p->ny * p->nz;
+    s->graph = GraphCache();
+    s->capture_stream = nullptr;
 
     if (p->init_mode == GS_INIT_CUBE) {
         hipError_t e = gs::launch_init_cube(p->storage, u0, v0, p->nx, p->ny, p->nz, p->cube_side, p->cube_u,
@@ -241,15 +323,11 @@ gs_status gs_step(gs_sim *s, int64_t n_steps)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     if (n_steps < 0) return fail(GS_ERR_INVALID_ARG, "n_steps = %lld < 0", (long long)n_steps);
-    for (int64_t i = 0; i < n_steps; ++i) {
-        gs::StepArgs a = make_args(s);
-        const int q = s->parity;
-        hipError_t e = gs::launch_step(s->p.storage, s->tile, s->buf[q][0], s->buf[q][1], s->buf[q ^ 1][0],
-                                       s->buf[q ^ 1][1], a, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "step kernel launch");
-        s->parity ^= 1;
-        s->step += 1;
-    }
+    int parity = s->parity;
+    hipError_t e = enqueue_steps(s, n_steps, s->stream, nullptr, &parity);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    s->parity = parity;
+    s->step += (uint64_t)n_steps;
     return GS_OK;
 }
 
@@ -377,9 +455,162 @@ gs_status gs_destroy(gs_sim *s)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     hipError_t e = hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    if (s->capture_stream) hipStreamDestroy(s->capture_stream);
     s->magic = 0;
     delete s;
     if (e != hipSuccess) return hip_fail(e, "gs_destroy sync");
+    return GS_OK;
+}
+
+gs_status gs_set_config(gs_sim *s, int32_t tile, int32_t tblock, int32_t zchunk)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    if (tile < 1 || tile > total_tiles()) return fail(GS_ERR_INVALID_ARG, "tile %d out of range", tile);
+    if (tblock < 1 || tblock > tile_max_tblock(tile))
+        return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, tile_max_tblock(tile), tile);
+    if (zchunk < 1) return fail(GS_ERR_INVALID_ARG, "zchunk %d < 1", zchunk);
+    s->tile = tile;
+    s->tblock = tblock;
+    s->zc = zchunk < s->p.nz ? zchunk : s->p.nz;
+    return GS_OK;
+}
+
+gs_status gs_get_config(gs_sim *s, int32_t *tile, int32_t *tblock, int32_t *zchunk)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    if (tile) *tile = s->tile;
+    if (tblock) *tblock = s->tblock;
+    if (zchunk) *zchunk = s->zc;
+    return GS_OK;
+}
+
+gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacity, int32_t *n_entries)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    if (reps < 1) return fail(GS_ERR_INVALID_ARG, "reps %d < 1", reps);
+    if (capacity < 0 || (capacity > 0 && !table)) return fail(GS_ERR_INVALID_ARG, "bad table/capacity");
+    static const int zcs[] = {16, 32, 64, 128, 256, 512};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_fail(e, "gs_tune events");
+    }
+    const int save_tile = s->tile, save_tb = s->tblock, save_zc = s->zc;
+    double best = 1e300;
+    int bt = save_tile, bT = save_tb, bz = save_zc;
+    int count = 0;
+    for (int tile = 1; tile <= total_tiles() && e == hipSuccess; ++tile) {
+        for (int T = 1; T <= tile_max_tblock(tile) && e == hipSuccess; ++T) {
+            int last_zc = -1;
+            for (int zi = 0; zi < (int)(sizeof zcs / sizeof zcs[0]) && e == hipSuccess; ++zi) {
+                const int zc = zcs[zi] < s->p.nz ? zcs[zi] : s->p.nz;
+                if (zc == last_zc) continue;
+                last_zc = zc;
+                s->tile = tile;
+                s->tblock = T;
+                s->zc = zc;
+                // Reads the current pair and writes the other one; the state
+                // and the step index are left unchanged.
+                int par = s->parity;
+                e = enqueue_steps(s, T, s->stream, nullptr, &par); // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                    par = s->parity;
+                    e = enqueue_steps(s, T, s->stream, nullptr, &par);
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) break;
+                const double per_step = (double)ms / (reps * T);
+                if (count < capacity) {
+                    table[count].tile = tile;
+                    table[count].tblock = T;
+                    table[count].zchunk = zc;
+                    table[count].reserved = 0;
+                    table[count].ms_per_step = per_step;
+                }
+                ++count;
+                if (per_step < best) {
+                    best = per_step;
+                    bt = tile;
+                    bT = T;
+                    bz = zc;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        s->tile = save_tile;
+        s->tblock = save_tb;
+        s->zc = save_zc;
+        return hip_fail(e, "gs_tune");
+    }
+    s->tile = bt;
+    s->tblock = bT;
+    s->zc = bz;
+    if (n_entries) *n_entries = count;
+    return GS_OK;
+}
+
+gs_status gs_step_graph(gs_sim *s, int64_t n_steps)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    if (n_steps < 0) return fail(GS_ERR_INVALID_ARG, "n_steps = %lld < 0", (long long)n_steps);
+    if (n_steps == 0) return GS_OK;
+    GraphCache &g = s->graph;
+    uint64_t *t_dev = (uint64_t *)((char *)s->ws + counter_offset());
+    hipError_t e = hipSuccess;
+    int end_parity = s->parity;
+    if (!(g.exec && g.n == n_steps && g.parity == s->parity && g.tile == s->tile && g.tblock == s->tblock &&
+          g.zc == s->zc)) {
+        drop_graph(s);
+        if (!s->capture_stream) {
+            e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "capture stream");
+        }
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        int par = s->parity;
+        hipError_t le = enqueue_steps(s, n_steps, s->capture_stream, t_dev, &par);
+        e = hipStreamEndCapture(s->capture_stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return hip_fail(le, "capture launches");
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g = GraphCache();
+            return hip_fail(e, "graph instantiate");
+        }
+        g.n = n_steps;
+        g.parity = s->parity;
+        g.tile = s->tile;
+        g.tblock = s->tblock;
+        g.zc = s->zc;
+    }
+    // The captured kernels take their step index from the device counter.
+    e = gs::launch_set_u64(t_dev, s->step, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "step counter");
+    e = hipGraphLaunch(g.exec, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    const int64_t launches = is_tb_tile(s->tile) ? (n_steps + s->tblock - 1) / s->tblock : n_steps;
+    if (launches & 1) end_parity ^= 1;
+    s->parity = end_parity;
+    s->step += (uint64_t)n_steps;
     return GS_OK;
 }
 

@@ -231,4 +231,16 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ counter
+__global__ void set_u64_kernel(uint64_t *dst, uint64_t value)
+{
+    if (threadIdx.x == 0) *dst = value;
+}
+
+hipError_t launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, st, dst, value);
+    return hipGetLastError();
+}
+
 } // namespace gs

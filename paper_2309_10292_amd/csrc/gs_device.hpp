@@ -76,14 +76,13 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a_lo = 0xD2511F53u * c0;
-        const uint32_t a_hi = __umulhi(0xD2511F53u, c0);
-        const uint32_t b_lo = 0xCD9E8D57u * c2;
-        const uint32_t b_hi = __umulhi(0xCD9E8D57u, c2);
-        c0 = b_hi ^ c1 ^ k0;
-        c1 = b_lo;
-        c2 = a_hi ^ c3 ^ k1;
-        c3 = a_lo;
+        // One 32x32 -> 64-bit multiply instruction per product (hi and lo together).
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)pb;
+        c2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)pa;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -16,7 +16,12 @@ struct StepArgs {
     float Du_f, Dv_f, F_f, FK_f, dt_f, noise_f;
     uint64_t seed;
     uint64_t t;          // global index of the step being taken (noise key)
+    // When non-null, the step index is *t_dev + t (graph replays read the
+    // base step from device memory so one captured graph serves every start).
+    const uint64_t *t_dev;
 };
+
+__host__ __device__ inline uint64_t step_index(const StepArgs &a) { return a.t_dev ? *a.t_dev + a.t : a.t; }
 
 template <typename C> struct Coef;
 template <> struct Coef<double> {
@@ -62,4 +67,16 @@ size_t diag_result_offset();
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
+// Writes `value` to *dst with a one-lane kernel (graph-safe; no memset node).
+hipError_t launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t st);
+
+} // namespace gs
+
+namespace gs {
+// Temporally blocked sweep: T steps (u, v) -> (un, vn) in one launch with
+// tile shape 1..num_tb_shapes().
+int num_tb_shapes();
+TileShape tb_shape(int shape, int T);
+hipError_t launch_tblock(int storage, int T, int shape, const void *u, const void *v, void *un, void *vn,
+                         const StepArgs &a, hipStream_t st);
 } // namespace gs

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
             if constexpr (NOISE) {
 #pragma unroll
                 for (int b = 0; b < V / 4; ++b) {
-                    const Philox4 w = noise_block(out_off + 4 * b, a.t, a.seed);
+                    const Philox4 w = noise_block(out_off + 4 * b, step_index(a), a.seed);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         if constexpr (sizeof(C) == 8)

@@ -1,0 +1,349 @@
+// Temporally blocked Gray-Scott sweep for gfx950: T = 1..4 time steps per
+// pass over HBM (Eq. 2a/2b applied T times with the Eq. 1a/1b sources and the
+// Eq. 3 Laplacian; periodic in x, y, z).
+//
+// One workgroup of NT lanes owns an output tile of TXG x-groups (4 cells
+// each) by TY rows and marches through a chunk of z planes. Level k (k = 0..T)
+// is the state after k of the T steps; level k is needed on the output tile
+// widened by T - k rows in y and by one x-group on each side in x (enough for
+// T <= 4). Every lane owns one x-group of the level-0 region and the same
+// position in every level; a level is computed only where that position lies
+// in its region.
+//
+// Per z iteration i (a wavefront in z):
+//   - level-0 plane i+1 enters (prefetched one iteration earlier);
+//   - for k = 1..T, level k computes plane i-k+1 from level k-1's planes
+//     i-k, i-k+1, i-k+2: z neighbours from the lane's registers (a 3-plane
+//     window per level), x and y neighbours from level k-1's current plane
+//     staged in LDS;
+//   - level T's plane is stored if it lies in the workgroup's chunk;
+//   - each level's newest plane is staged in LDS for the next iteration.
+// Cells are evaluated by the same operation sequence as the single-step
+// kernel, so results are bitwise independent of T and of the tile. The noise
+// of level k uses step index t + k - 1.
+#include "gs_device.hpp"
+#include "gs_launch.hpp"
+
+namespace gs {
+
+template <typename S, int TXG, int TY, int T, int NT> struct TbGeom {
+    typedef typename Traits<S>::C C;
+    static constexpr int GX = TXG + 2;          // x-groups per region row
+    static constexpr int RW = GX * 4;           // region row width (cells)
+    static constexpr int H = 16 / (int)sizeof(C);  // LDS row pad (>= 1; keeps rows 16-byte aligned)
+    static constexpr int RS = RW + 2 * H;       // LDS row stride
+    static constexpr int RY0 = TY + 2 * T;      // level-0 rows
+    static constexpr int NSLOT = GX * RY0;      // lanes with a level-0 position
+    // LDS rows of levels 0..T-1: RY0 - 2k each.
+    static constexpr int LDS_ROWS = T * RY0 - T * (T - 1);
+    static constexpr int FIELD = LDS_ROWS * RS; // elements per field
+    static_assert(T >= 1 && T <= 4, "one pad group covers at most 4 levels");
+    static_assert(NSLOT <= NT, "every level-0 position needs a lane");
+    static constexpr int row_base(int k) { return k * RY0 - k * (k - 1); }
+};
+
+template <typename S> struct NtStore;
+template <> struct NtStore<double> {
+    static __device__ __forceinline__ void put(double *p, const Vec<double, 4> &v)
+    {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        d2 a = {v.e[0], v.e[1]}, b = {v.e[2], v.e[3]};
+        __builtin_nontemporal_store(a, reinterpret_cast<d2 *>(p));
+        __builtin_nontemporal_store(b, reinterpret_cast<d2 *>(p) + 1);
+    }
+};
+template <> struct NtStore<float> {
+    static __device__ __forceinline__ void put(float *p, const Vec<float, 4> &v)
+    {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 a = {v.e[0], v.e[1], v.e[2], v.e[3]};
+        __builtin_nontemporal_store(a, reinterpret_cast<f4 *>(p));
+    }
+};
+template <> struct NtStore<bf16> {
+    static __device__ __forceinline__ void put(bf16 *p, const Vec<bf16, 4> &v)
+    {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        u2 a = {(unsigned)v.e[0].bits | ((unsigned)v.e[1].bits << 16), (unsigned)v.e[2].bits | ((unsigned)v.e[3].bits << 16)};
+        __builtin_nontemporal_store(a, reinterpret_cast<u2 *>(p));
+    }
+};
+template <> struct NtStore<f16> {
+    static __device__ __forceinline__ void put(f16 *p, const Vec<f16, 4> &v)
+    {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        h4 a = {v.e[0], v.e[1], v.e[2], v.e[3]};
+        __builtin_nontemporal_store(a, reinterpret_cast<h4 *>(p));
+    }
+};
+
+template <typename C>
+__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, bool noisy, C r, C &uo, C &vo)
+{
+    const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
+    const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
+    const C uvv = uc * (vc * vc);
+    C du = (Du * lu - uvv) + F * ((C)1 - uc);
+    if (noisy) du = du + Coef<C>::noise(a) * r;
+    const C dv = (Dv * lv + uvv) - FK * vc;
+    uo = uc + du * dt;
+    vo = vc + dv * dt;
+}
+
+template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
+__global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const S *__restrict__ v,
+                                                 S *__restrict__ un, S *__restrict__ vn, StepArgs a)
+{
+    typedef TbGeom<S, TXG, TY, T, NT> G;
+    typedef typename G::C C;
+    __shared__ C lds[2 * G::FIELD];
+
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % (uint32_t)a.ntx);
+    const uint32_t rest = lb / (uint32_t)a.ntx;
+    const int by = (int)(rest % (uint32_t)a.nty);
+    const int bz = (int)(rest / (uint32_t)a.nty);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x0 = bx * (TXG * 4), y0 = by * TY, z0 = bz * a.zc;
+    const int ze = min(z0 + a.zc, nz);
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const uint64_t t0 = NOISE ? step_index(a) : 0;
+
+    // This lane's position: x-group gxs, level-0 row rys.
+    const int s = threadIdx.x;
+    const bool has = s < G::NSLOT;
+    const int gxs = s % G::GX;
+    const int rys = has ? s / G::GX : 0;
+    const int gx = (((x0 - 4 + 4 * gxs) % nx) + nx) % nx;
+    const int gy = (((y0 - T + rys) % ny) + ny) % ny;
+    const size_t xy = (size_t)gy * nx + gx;
+    // Output position (level T) and whether this lane stores it.
+    const bool out_slot = has && gxs >= 1 && gxs <= TXG && rys >= T && rys < T + TY;
+    const bool out_ok = out_slot && (x0 + 4 * (gxs - 1) < nx) && (y0 + rys - T < ny);
+
+    C win[T][3][2][4]; // [level][m, c, p][field][cell]
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) win[k][q][f][e] = (C)0;
+
+    const S *src[2] = {u, v};
+    auto load_plane = [&](int z, Vec<S, 4> (&o)[2]) {
+        const size_t off = (size_t)wrap(z, nz) * plane + xy;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) o[f] = *reinterpret_cast<const Vec<S, 4> *>(src[f] + off);
+    };
+    auto lds_at = [&](int f, int k, int row, int col) -> C & {
+        return lds[f * G::FIELD + (G::row_base(k) + row) * G::RS + G::H + col];
+    };
+    auto in_level = [&](int k) { return has && rys >= k && rys < G::RY0 - k; };
+
+    // Prologue: level-0 window holds planes z0-T, z0-T+1, z0-T+2; LDS holds z0-T+1.
+    const int i0 = z0 - T + 1;
+    const int i_end = ze + T - 2; // inclusive
+    Vec<S, 4> pre[2];
+    if (has) {
+        Vec<S, 4> t0[2], t1[2];
+        load_plane(i0 - 1, t0);
+        load_plane(i0, t1);
+        load_plane(i0 + 1, pre);
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                win[0][1][f][e] = Traits<S>::load(t0[f].e[e]);
+                win[0][2][f][e] = Traits<S>::load(t1[f].e[e]);
+            }
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][2][f][e];
+    }
+    __syncthreads();
+
+    for (int i = i0; i <= i_end; ++i) {
+        // Level 0: plane i+1 enters the window; prefetch plane i+2.
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                win[0][0][f][e] = win[0][1][f][e];
+                win[0][1][f][e] = win[0][2][f][e];
+                win[0][2][f][e] = Traits<S>::load(pre[f].e[e]);
+            }
+        if (has && i + 2 <= ze + T - 1) load_plane(i + 2, pre);
+
+        // Levels 1..T, in order; level k computes plane i-k+1.
+#pragma unroll
+        for (int k = 1; k <= T; ++k) {
+            const int zk = i - k + 1;
+            C res[2][4];
+            if (in_level(k)) {
+                const int row = rys - (k - 1); // row of this position in level k-1's LDS plane
+                C xm[2][4], xp[2][4], ym[2][4], yp[2][4];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    const C *c = win[k - 1][1][f];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        xm[f][e] = e > 0 ? c[e - 1] : lds_at(f, k - 1, row, 4 * gxs - 1);
+                        xp[f][e] = e < 3 ? c[e + 1] : lds_at(f, k - 1, row, 4 * gxs + 4);
+                        ym[f][e] = lds_at(f, k - 1, row - 1, 4 * gxs + e);
+                        yp[f][e] = lds_at(f, k - 1, row + 1, 4 * gxs + e);
+                    }
+                }
+                C r[4] = {(C)0, (C)0, (C)0, (C)0};
+                if constexpr (NOISE) {
+                    const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
+                    const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if constexpr (sizeof(C) == 8)
+                            r[e] = noise_word_f64(w.w[e]);
+                        else
+                            r[e] = noise_word_f32(w.w[e]);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const C uc = win[k - 1][1][0][e], vc = win[k - 1][1][1][e];
+                    C lu, lv;
+                    if constexpr (sizeof(C) == 8) {
+                        lu = lap_f64(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][0][0][e], win[k - 1][2][0][e]);
+                        lv = lap_f64(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][0][1][e], win[k - 1][2][1][e]);
+                    } else {
+                        lu = lap_comp_f32(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][0][0][e], win[k - 1][2][0][e]);
+                        lv = lap_comp_f32(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][0][1][e], win[k - 1][2][1][e]);
+                    }
+                    C uo, vo;
+                    cell_update<C>(a, uc, vc, lu, lv, NOISE, r[e], uo, vo);
+                    // Intermediate levels carry the stored precision of the state.
+                    res[0][e] = Traits<S>::load(Traits<S>::store(uo));
+                    res[1][e] = Traits<S>::load(Traits<S>::store(vo));
+                }
+            } else {
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) res[f][e] = (C)0;
+            }
+            if (k < T) {
+                // Rotate level k's window: the new plane becomes 'p'.
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        win[k][0][f][e] = win[k][1][f][e];
+                        win[k][1][f][e] = win[k][2][f][e];
+                        win[k][2][f][e] = res[f][e];
+                    }
+            } else if (out_ok && zk >= z0) {
+                Vec<S, 4> ou, ov;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ou.e[e] = Traits<S>::store(res[0][e]);
+                    ov.e[e] = Traits<S>::store(res[1][e]);
+                }
+                const size_t off = (size_t)zk * plane + xy;
+                NtStore<S>::put(un + off, ou);
+                NtStore<S>::put(vn + off, ov);
+            }
+        }
+        __syncthreads(); // all reads of the staged planes are done
+        // Stage the newest plane of levels 0..T-1 (the centre plane of the next iteration).
+        if (has) {
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][2][f][e];
+        }
+#pragma unroll
+        for (int k = 1; k < T; ++k) {
+            if (in_level(k)) {
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, 4 * gxs + e) = win[k][2][f][e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ launch
+template <typename S, int TXG, int TY, int T, int NT>
+static hipError_t launch_tb_t(const void *u, const void *v, void *un, void *vn, StepArgs a, hipStream_t st)
+{
+    a.ntx = (a.nx + TXG * 4 - 1) / (TXG * 4);
+    a.nty = (a.ny + TY - 1) / TY;
+    const int nzc = (a.nz + a.zc - 1) / a.zc;
+    const size_t nb = (size_t)a.ntx * a.nty * nzc;
+    if (nb == 0 || nb > 0x7fffffffu) return hipErrorInvalidConfiguration;
+    if (a.noise != 0.0)
+        hipLaunchKernelGGL((stencil_tb<S, TXG, TY, T, NT, true>), dim3((unsigned)nb), dim3(NT), 0, st,
+                           (const S *)u, (const S *)v, (S *)un, (S *)vn, a);
+    else
+        hipLaunchKernelGGL((stencil_tb<S, TXG, TY, T, NT, false>), dim3((unsigned)nb), dim3(NT), 0, st,
+                           (const S *)u, (const S *)v, (S *)un, (S *)vn, a);
+    return hipGetLastError();
+}
+
+// Shapes per T (output x-groups, rows, lanes): the level-0 region
+// (TXG + 2) x (TY + 2T) fills the workgroup.
+//   shape 1: TXG=16, 256 lanes, region 18 x 14
+//   shape 2: TXG=16, 512 lanes, region 18 x 28
+//   shape 3: TXG=32, 512 lanes, region 34 x 14
+template <typename S, int T>
+static hipError_t dispatch_tb_shape(int shape, const void *u, const void *v, void *un, void *vn, const StepArgs &a,
+                                    hipStream_t st)
+{
+    switch (shape) {
+    case 1: return launch_tb_t<S, 16, 14 - 2 * T, T, 256>(u, v, un, vn, a, st);
+    case 2: return launch_tb_t<S, 16, 28 - 2 * T, T, 512>(u, v, un, vn, a, st);
+    case 3: return launch_tb_t<S, 32, 14 - 2 * T, T, 512>(u, v, un, vn, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename S>
+static hipError_t dispatch_tb_T(int T, int shape, const void *u, const void *v, void *un, void *vn,
+                                const StepArgs &a, hipStream_t st)
+{
+    switch (T) {
+    case 1: return dispatch_tb_shape<S, 1>(shape, u, v, un, vn, a, st);
+    case 2: return dispatch_tb_shape<S, 2>(shape, u, v, un, vn, a, st);
+    case 3: return dispatch_tb_shape<S, 3>(shape, u, v, un, vn, a, st);
+    case 4: return dispatch_tb_shape<S, 4>(shape, u, v, un, vn, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int num_tb_shapes() { return 3; }
+
+TileShape tb_shape(int shape, int T)
+{
+    switch (shape) {
+    case 1: return TileShape{64, 14 - 2 * T};
+    case 2: return TileShape{64, 28 - 2 * T};
+    case 3: return TileShape{128, 14 - 2 * T};
+    }
+    return TileShape{0, 0};
+}
+
+hipError_t launch_tblock(int storage, int T, int shape, const void *u, const void *v, void *un, void *vn,
+                         const StepArgs &a, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return dispatch_tb_T<double>(T, shape, u, v, un, vn, a, st);
+    case 1: return dispatch_tb_T<float>(T, shape, u, v, un, vn, a, st);
+    case 2: return dispatch_tb_T<bf16>(T, shape, u, v, un, vn, a, st);
+    case 3: return dispatch_tb_T<f16>(T, shape, u, v, un, vn, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+} // namespace gs

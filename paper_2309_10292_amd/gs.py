@@ -31,7 +31,8 @@ class gs_params(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("step0", ctypes.c_uint64),
                 ("init_mode", ctypes.c_int32), ("cube_side", ctypes.c_int32),
                 ("cube_u", ctypes.c_double), ("cube_v", ctypes.c_double),
-                ("tblock", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("tblock", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class gs_diag(ctypes.Structure):
@@ -39,6 +40,11 @@ class gs_diag(ctypes.Structure):
                 ("min_u", ctypes.c_double), ("max_u", ctypes.c_double),
                 ("min_v", ctypes.c_double), ("max_v", ctypes.c_double),
                 ("nonfinite", ctypes.c_int64)]
+
+
+class gs_tune_entry(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("tblock", ctypes.c_int32), ("zchunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
 class GSError(RuntimeError):
@@ -58,7 +64,7 @@ SIGNATURES = [
     ("gs_last_error", ctypes.c_char_p, []),
     ("gs_workspace_bytes", _SZ, [_PP]),
     ("gs_num_tiles", _I32, []),
-    ("gs_tile_info", _I32, [_I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("gs_tile_info", _I32, [_I32, _I32, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("gs_init", _I32, [_PP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(_SIM)]),
     ("gs_step", _I32, [_SIM, _I64]),
     ("gs_read", _I32, [_SIM, _DP, _DP]),
@@ -67,6 +73,10 @@ SIGNATURES = [
     ("gs_diagnostics", _I32, [_SIM, ctypes.POINTER(gs_diag)]),
     ("gs_sync", _I32, [_SIM]),
     ("gs_destroy", _I32, [_SIM]),
+    ("gs_set_config", _I32, [_SIM, _I32, _I32, _I32]),
+    ("gs_get_config", _I32, [_SIM, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("gs_tune", _I32, [_SIM, _I32, ctypes.c_void_p, _I32, ctypes.POINTER(_I32)]),
+    ("gs_step_graph", _I32, [_SIM, _I64]),
     ("gs_laplacian7", _I32, [_VP, _VP, _I32, _I32, _I32, _VP]),
     ("gs_copy", _I32, [_VP, _VP, _SZ, _VP]),
 ]
@@ -98,7 +108,7 @@ def check(status: int):
 
 
 def make_params(nx, ny, nz, *, storage="f64", Du=0.2, Dv=0.1, F=0.02, k=0.048, dt=1.0, noise=0.0,
-                seed=0, step0=0, init="cube", cube_side=12, cube_u=0.25, cube_v=0.33, tblock=0, tile=0):
+                seed=0, step0=0, init="cube", cube_side=12, cube_u=0.25, cube_v=0.33, tblock=0, tile=0, zchunk=0):
     p = gs_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     p.storage = DTYPES[storage] if isinstance(storage, str) else int(storage)
@@ -106,7 +116,7 @@ def make_params(nx, ny, nz, *, storage="f64", Du=0.2, Dv=0.1, F=0.02, k=0.048, d
     p.seed, p.step0 = int(seed), int(step0)
     p.init_mode = INIT_CUBE if init == "cube" else INIT_NONE
     p.cube_side, p.cube_u, p.cube_v = int(cube_side), float(cube_u), float(cube_v)
-    p.tblock, p.tile = int(tblock), int(tile)
+    p.tblock, p.tile, p.zchunk = int(tblock), int(tile), int(zchunk)
     return p
 
 
@@ -160,6 +170,29 @@ class Sim:
 
     def step(self, n: int = 1):
         check(load().gs_step(self.h, int(n)))
+
+    def step_graph(self, n: int):
+        """Same as step(n), replayed from a captured HIP graph."""
+        check(load().gs_step_graph(self.h, int(n)))
+
+    def set_config(self, tile: int, tblock: int, zchunk: int):
+        check(load().gs_set_config(self.h, int(tile), int(tblock), int(zchunk)))
+
+    def config(self):
+        t, b, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(load().gs_get_config(self.h, ctypes.byref(t), ctypes.byref(b), ctypes.byref(z)))
+        return dict(tile=t.value, tblock=b.value, zchunk=z.value)
+
+    def tune(self, reps: int = 3):
+        """Autotune the launch configuration on this grid (state unchanged).
+        Returns (chosen config, list of measured candidates)."""
+        cap = 256
+        table = (gs_tune_entry * cap)()
+        n = ctypes.c_int32()
+        check(load().gs_tune(self.h, int(reps), ctypes.cast(table, ctypes.c_void_p), cap, ctypes.byref(n)))
+        rows = [dict(tile=e.tile, tblock=e.tblock, zchunk=e.zchunk, ms_per_step=e.ms_per_step)
+                for e in table[:min(n.value, cap)]]
+        return self.config(), rows
 
     def read(self):
         u = np.empty(self.shape, dtype=np.float64)

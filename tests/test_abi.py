@@ -83,6 +83,8 @@ def _init_status(**kw):
     (dict(cube_side=65), gs.GS_ERR_INVALID_ARG),
     (dict(tblock=gs.MAX_TBLOCK + 1), gs.GS_ERR_INVALID_ARG),
     (dict(tile=99), gs.GS_ERR_INVALID_ARG),
+    (dict(tile=1, tblock=2), gs.GS_ERR_INVALID_ARG),
+    (dict(zchunk=-1), gs.GS_ERR_INVALID_ARG),
     (dict(), gs.GS_ERR_INVALID_ARG),  # valid params, NULL buffers
 ])
 def test_init_validation(kw, status):
@@ -131,7 +133,11 @@ def test_workspace_and_tiles():
     assert n >= 1
     for t in range(1, n + 1):
         for s in range(4):
-            tx, ty, zc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-            assert L.gs_tile_info(t, s, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(zc)) == gs.GS_OK
-            assert tx.value > 0 and ty.value > 0 and zc.value > 0
-    assert L.gs_tile_info(0, 0, None, None, None) == gs.GS_ERR_INVALID_ARG
+            tx, ty, mt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            assert L.gs_tile_info(t, s, 1, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(mt)) == gs.GS_OK
+            assert tx.value > 0 and ty.value > 0 and mt.value >= 1
+            for T in range(1, mt.value + 1):
+                assert L.gs_tile_info(t, s, T, ctypes.byref(tx), ctypes.byref(ty), None) == gs.GS_OK
+                assert ty.value > 0
+            assert L.gs_tile_info(t, s, mt.value + 1, None, None, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_tile_info(0, 0, 1, None, None, None) == gs.GS_ERR_INVALID_ARG

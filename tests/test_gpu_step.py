@@ -248,3 +248,111 @@ def test_full_size_l1024_fp64_sampled(torch):
         corners = [(c, c, c), (c - 8, c + 4, c - 2), (c + 10, c - 10, c + 5), (0, 0, 0), (1016, 1016, 1016)]
         _sampled_windows(prev, (u_t, v_t), shape, dict(p), p["steps"] - 4, 4, corners)
         del prev
+
+
+TB_TILES = (5, 6, 7)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
+def test_tblock_bitwise_vs_oracle(torch, T):
+    """The temporally blocked kernel (T steps per pass, every shape) against the
+    oracle on ragged periodic grids with noise; step counts that are not
+    multiples of T exercise the remainder launch."""
+    for shape in [(20, 36, 40), (9, 13, 24), (70, 5, 16), (4, 4, 8)]:
+        u0, v0 = random_state(shape, seed=7 * T + sum(shape), lo_u=0.2, hi_u=1.0, lo_v=0.0, hi_v=0.5)
+        p = dict(Du=0.19, Dv=0.11, F=0.029, k=0.055, dt=0.9, noise=0.01, seed=4242, step0=77)
+        n = 2 * T + 1
+        ue, ve = O.run(u0, v0, n, **p)
+        for tile in TB_TILES:
+            with _sim(shape, u0=u0, v0=v0, tile=tile, tblock=T, zchunk=16, **p) as s:
+                s.step(n)
+                u, v = s.read()
+            assert np.array_equal(u, ue) and np.array_equal(v, ve), \
+                f"T={T} tile={tile} shape={shape}: {max_abs(u, ue)} {max_abs(v, ve)}"
+
+
+def test_tblock_small_l64_fp64_bitwise(torch, small_ref):
+    p = workload("small_l64")
+    for T in (2, 4):
+        for tile in TB_TILES:
+            with _sim((64, 64, 64), tile=tile, tblock=T, **P0) as s:
+                s.step(p["steps"])
+                u, v = s.read()
+            assert np.array_equal(u, small_ref[0]) and np.array_equal(v, small_ref[1]), (T, tile)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_tblock_reduced_precision_equals_single_step(torch, storage):
+    """Reduced-precision storage: T fused steps round every intermediate level
+    to the storage type, so they equal T single-step sweeps bit for bit."""
+    shape = (24, 40, 48)
+    p = dict(P0, noise=1e-3, seed=11)
+    with _sim(shape, storage=storage, tile=1, cube_side=10, **p) as s:
+        s.step(9)
+        ref = s.current()
+        ref = (ref[0].clone(), ref[1].clone())
+    for T in (2, 3, 4):
+        with _sim(shape, storage=storage, tile=5, tblock=T, cube_side=10, **p) as s:
+            s.step(9)
+            u_t, v_t, st = s.current()
+            assert st == 9
+            assert torch.equal(u_t, ref[0]) and torch.equal(v_t, ref[1]), (storage, T)
+
+
+def test_tblock_full_size_l512_noise(torch):
+    """The benchmarked configuration class at full size: L=512, noise 1e-7,
+    T=2 temporally blocked sweeps; 10 steps compared over the whole field."""
+    p = workload("weak_share_l512")
+    L = p["L"]
+    kw = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
+    with _sim((L, L, L), tile=5, tblock=2, **kw) as s:
+        s.step(10)
+        u, v = s.read()
+    u0, v0 = O.init_cube(L=L)
+    ue, ve = O.run(u0, v0, 10, **p)
+    assert np.array_equal(u, ue) and np.array_equal(v, ve), max_abs(u, ue)
+
+
+def test_graph_replay_matches_eager(torch):
+    """gs_step_graph: several replays of one captured graph, with eager work
+    and synchronisations between them, each checked against eager stepping
+    (noise on, so a wrong step index in a replay would show)."""
+    shape = (32, 40, 48)
+    p = dict(P0, noise=0.01, seed=8)
+    for tile, T in ((1, 1), (6, 3), (5, 2)):
+        with _sim(shape, tile=tile, tblock=T, cube_side=12, **p) as eager, \
+                _sim(shape, tile=tile, tblock=T, cube_side=12, **p) as g:
+            for rep in range(4):
+                eager.step(7)
+                g.step_graph(7)
+                a, b = eager.current(), g.current()
+                assert a[2] == b[2]
+                assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), (tile, T, rep)
+                # eager work on the graph's handle between replays
+                g.step(1)
+                eager.step(1)
+                torch.cuda.synchronize()
+            ue, ve = eager.read()
+        u0, v0 = O.init_cube(shape=shape, side=12)
+        uo, vo = O.run(u0, v0, 32, **p)
+        assert np.array_equal(ue, uo) and np.array_equal(ve, vo)
+
+
+def test_tune_leaves_state_and_picks_valid_config(torch):
+    shape = (64, 64, 128)
+    p = dict(P0, noise=1e-3, seed=21)
+    with _sim(shape, cube_side=20, **p) as s:
+        s.step(3)
+        before = s.read()
+        cfg, rows = s.tune(reps=1)
+        after = s.read()
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        assert s.current()[2] == 3
+        assert len(rows) > 10 and all(r["ms_per_step"] > 0 for r in rows)
+        best = min(rows, key=lambda r: r["ms_per_step"])
+        assert (cfg["tile"], cfg["tblock"], cfg["zchunk"]) == (best["tile"], best["tblock"], best["zchunk"])
+        s.step(5)
+        u, v = s.read()
+    u0, v0 = O.init_cube(shape=shape, side=20)
+    ue, ve = O.run(u0, v0, 8, **p)
+    assert np.array_equal(u, ue) and np.array_equal(v, ve)
