@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--tblock", type=int, default=0, help="fused steps per sweep, 0 = library choice")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per workgroup chunk, 0 = library choice")
     ap.add_argument("--tune", action="store_true", help="autotune the launch configuration first")
-XX
+    ap.add_argument("--variants", default="f32,bf16,f16", help="other storage types to time, or 'none'")
     ap.add_argument("--variant-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
