@@ -182,6 +182,67 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
 gs_status gs_step_graph(gs_sim *s, int64_t n_steps);
 
 /* ------------------------------------------------------------------ */
+/* Batched sweeps: many independent simulations (own grid and own F, k; shared
+ * Du, Dv, dt, noise, storage) advanced together by persistent launches of the
+ * temporally blocked kernel. Simulation i draws its noise with key seed + i.
+ * Every simulation has a launch configuration (tile among the temporally
+ * blocked tiles, tblock, zchunk >= 8); simulations sharing (tile, tblock) are
+ * advanced by one persistent launch per tblock steps. */
+
+typedef struct gs_batch gs_batch; /* opaque handle */
+
+typedef struct gs_batch_tune_entry {
+    int32_t nx, ny, nz, n_sims;       /* the grid class and how many simulations have it */
+    int32_t tile, tblock, zchunk, reserved; /* the configuration chosen for it */
+    double ms_per_step;               /* time per step of all its simulations together */
+    double gcells;                    /* their cell-updates per second, in units of 1e9 */
+} gs_batch_tune_entry;
+
+/* Device bytes of the fields of all simulations (4 buffers each, 256-byte
+ * aligned) and of the batch workspace (descriptors, work lists, diagnostic
+ * partials); 0 for invalid arguments. */
+size_t gs_batch_arena_bytes(int32_t storage, int32_t n_sims, const int32_t *nx, const int32_t *ny,
+                            const int32_t *nz);
+size_t gs_batch_workspace_bytes(int32_t n_sims, const int32_t *nx, const int32_t *ny, const int32_t *nz);
+
+/* `base` gives storage, Du, Dv, dt, noise, seed, step0, init (the cube of
+ * cube_side centred in every grid) and optionally tile/tblock/zchunk for all
+ * simulations (0 = library choice); its nx, ny, nz, F and k are ignored.
+ * nx, ny, nz, F, k are host arrays of n_sims entries; each grid follows the
+ * gs_params rules. `arena` and `workspace` are caller-owned device memory of
+ * at least the sizes above. Synchronising (uploads the work lists). */
+gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx, const int32_t *ny,
+                        const int32_t *nz, const double *F, const double *k, void *arena, size_t arena_bytes,
+                        void *workspace, size_t workspace_bytes, void *hip_stream, gs_batch **out);
+
+/* Advance every simulation by n_steps (asynchronous), directly or as one
+ * captured HIP graph replay (same result). */
+gs_status gs_batch_step(gs_batch *b, int64_t n_steps);
+gs_status gs_batch_step_graph(gs_batch *b, int64_t n_steps);
+
+/* Configuration of one simulation (sim >= 0) or of all (sim == -1); applied
+ * at the next step call. */
+gs_status gs_batch_set_config(gs_batch *b, int32_t sim, int32_t tile, int32_t tblock, int32_t zchunk);
+gs_status gs_batch_get_config(gs_batch *b, int32_t sim, int32_t *tile, int32_t *tblock, int32_t *zchunk);
+
+/* Synchronising autotuner: for every distinct grid size, times each
+ * (tile, tblock, zchunk) candidate on the simulations of that size (their
+ * states and the step index stay unchanged) and assigns the fastest to them.
+ * One entry per grid size is written to `table` (up to `capacity`);
+ * *n_entries receives the number of grid sizes. */
+gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, int32_t capacity,
+                        int32_t *n_entries);
+
+/* Per-simulation access, as gs_current / gs_read / gs_write / gs_diagnostics. */
+gs_status gs_batch_current(gs_batch *b, int32_t sim, void **u_dev, void **v_dev, uint64_t *step);
+gs_status gs_batch_read(gs_batch *b, int32_t sim, double *u_host, double *v_host);
+gs_status gs_batch_write(gs_batch *b, int32_t sim, const double *u_host, const double *v_host);
+gs_status gs_batch_diagnostics(gs_batch *b, int32_t sim, gs_diag *out);
+
+gs_status gs_batch_sync(gs_batch *b);
+gs_status gs_batch_destroy(gs_batch *b);
+
+/* ------------------------------------------------------------------ */
 /* Calibration kernels (measure the single-field stencil and plain streaming
  * on the same device, the analogue of the paper's Table 2 / Table 3 rows). */
 

@@ -2,6 +2,7 @@
 // ping-pong parity, host <-> device conversion, launch selection.
 #include "../../include/gs.h"
 #include "gs_launch.hpp"
+#include "gs_internal.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -13,7 +14,7 @@
 #include <string>
 #include <vector>
 
-namespace {
+namespace gsapi {
 
 thread_local std::string g_err;
 
@@ -109,7 +110,80 @@ float host_from_bf16(uint16_t b)
     return f;
 }
 
-} // namespace
+gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, hipStream_t st)
+{
+    const size_t es = storage_bytes(storage);
+    if (storage == GS_F64) {
+        hipError_t e = hipMemcpyAsync(host, dev, n * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e == hipSuccess ? GS_OK : hip_fail(e, "device-to-host copy");
+    }
+    std::vector<unsigned char> stage(n * es);
+    hipError_t e = hipMemcpyAsync(stage.data(), dev, n * es, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "device-to-host copy");
+    if (storage == GS_F32) {
+        const float *x = (const float *)stage.data();
+        for (size_t i = 0; i < n; ++i) host[i] = x[i];
+    } else if (storage == GS_BF16) {
+        const uint16_t *x = (const uint16_t *)stage.data();
+        for (size_t i = 0; i < n; ++i) host[i] = host_from_bf16(x[i]);
+    } else {
+        const _Float16 *x = (const _Float16 *)stage.data();
+        for (size_t i = 0; i < n; ++i) host[i] = (double)(float)x[i];
+    }
+    return GS_OK;
+}
+
+gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, hipStream_t st)
+{
+    const size_t es = storage_bytes(storage);
+    std::vector<unsigned char> stage;
+    const void *src = host;
+    if (storage != GS_F64) {
+        stage.resize(n * es);
+        if (storage == GS_F32) {
+            float *d = (float *)stage.data();
+            for (size_t i = 0; i < n; ++i) d[i] = (float)host[i];
+        } else if (storage == GS_BF16) {
+            uint16_t *d = (uint16_t *)stage.data();
+            for (size_t i = 0; i < n; ++i) d[i] = host_bf16((float)host[i]);
+        } else {
+            _Float16 *d = (_Float16 *)stage.data();
+            for (size_t i = 0; i < n; ++i) d[i] = (_Float16)(float)host[i];
+        }
+        src = stage.data();
+    }
+    hipError_t e = hipMemcpyAsync(dev, src, n * es, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "host-to-device copy");
+}
+
+gs_status diagnostics(int32_t storage, const void *u, const void *v, size_t n, void *ws, hipStream_t st,
+                      gs_diag *out)
+{
+    hipError_t e = gs::launch_diagnostics(storage, u, v, n, ws, st);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+    double r[9];
+    e = hipMemcpyAsync(r, (char *)ws + gs::diag_result_offset(), sizeof r, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
+    out->sum_u = r[0] + r[1];
+    out->sum_v = r[2] + r[3];
+    out->min_u = r[4];
+    out->max_u = r[5];
+    out->min_v = r[6];
+    out->max_v = r[7];
+    out->nonfinite = (int64_t)r[8];
+    if (out->nonfinite > 0) return fail(GS_ERR_NONFINITE, "%lld non-finite values", (long long)out->nonfinite);
+    return GS_OK;
+}
+
+size_t counter_offset() { return (gs::diag_workspace_bytes() + 255) / 256 * 256; }
+
+} // namespace gsapi
+
+using namespace gsapi;
 
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -245,8 +319,6 @@ const char *gs_last_error(void) { return g_err.c_str(); }
 
 // Workspace layout: diagnostic partials, then (256-byte aligned) the step
 // counter read by graph replays.
-size_t counter_offset() { return (gs::diag_workspace_bytes() + 255) / 256 * 256; }
-
 size_t gs_workspace_bytes(const gs_params *p)
 {
     if (validate(p) != GS_OK) return 0;
@@ -336,39 +408,13 @@ gs_status gs_read(gs_sim *s, double *u_host, double *v_host)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     double *dst[2] = {u_host, v_host};
-    const size_t es = storage_bytes(s->p.storage);
-    std::vector<unsigned char> stage;
     for (int f = 0; f < 2; ++f) {
         if (!dst[f]) continue;
-        const void *src = s->buf[s->parity][f];
-        if (s->p.storage == GS_F64) {
-            hipError_t e = hipMemcpyAsync(dst[f], src, s->n * 8, hipMemcpyDeviceToHost, s->stream);
-            if (e != hipSuccess) return hip_fail(e, "gs_read copy");
-            e = hipStreamSynchronize(s->stream);
-            if (e != hipSuccess) return hip_fail(e, "gs_read sync");
-            continue;
-        }
-        stage.resize(s->n * es);
-        hipError_t e = hipMemcpyAsync(stage.data(), src, s->n * es, hipMemcpyDeviceToHost, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "gs_read copy");
-        e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return hip_fail(e, "gs_read sync");
-        double *d = dst[f];
-        if (s->p.storage == GS_F32) {
-            const float *x = (const float *)stage.data();
-            for (size_t i = 0; i < s->n; ++i) d[i] = x[i];
-        } else if (s->p.storage == GS_BF16) {
-            const uint16_t *x = (const uint16_t *)stage.data();
-            for (size_t i = 0; i < s->n; ++i) d[i] = host_from_bf16(x[i]);
-        } else {
-            const _Float16 *x = (const _Float16 *)stage.data();
-            for (size_t i = 0; i < s->n; ++i) d[i] = (double)(float)x[i];
-        }
+        st = read_field(s->buf[s->parity][f], s->p.storage, s->n, dst[f], s->stream);
+        if (st != GS_OK) return st;
     }
-    if (!u_host && !v_host) {
-        hipError_t e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return hip_fail(e, "gs_read sync");
-    }
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_read sync");
     return GS_OK;
 }
 
@@ -377,32 +423,12 @@ gs_status gs_write(gs_sim *s, const double *u_host, const double *v_host)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     const double *srcs[2] = {u_host, v_host};
-    const size_t es = storage_bytes(s->p.storage);
-    std::vector<unsigned char> stage;
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "gs_write sync");
     for (int f = 0; f < 2; ++f) {
         if (!srcs[f]) continue;
-        const double *x = srcs[f];
-        const void *host = x;
-        if (s->p.storage != GS_F64) {
-            stage.resize(s->n * es);
-            if (s->p.storage == GS_F32) {
-                float *d = (float *)stage.data();
-                for (size_t i = 0; i < s->n; ++i) d[i] = (float)x[i];
-            } else if (s->p.storage == GS_BF16) {
-                uint16_t *d = (uint16_t *)stage.data();
-                for (size_t i = 0; i < s->n; ++i) d[i] = host_bf16((float)x[i]);
-            } else {
-                _Float16 *d = (_Float16 *)stage.data();
-                for (size_t i = 0; i < s->n; ++i) d[i] = (_Float16)(float)x[i];
-            }
-            host = stage.data();
-        }
-        e = hipMemcpyAsync(s->buf[s->parity][f], host, s->n * es, hipMemcpyHostToDevice, s->stream);
-        if (e != hipSuccess) return hip_fail(e, "gs_write copy");
-        e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) return hip_fail(e, "gs_write sync");
+        st = write_field(s->buf[s->parity][f], s->p.storage, s->n, srcs[f], s->stream);
+        if (st != GS_OK) return st;
     }
     return GS_OK;
 }
@@ -422,23 +448,7 @@ gs_status gs_diagnostics(gs_sim *s, gs_diag *out)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     if (!out) return fail(GS_ERR_INVALID_ARG, "out is NULL");
-    hipError_t e = gs::launch_diagnostics(s->p.storage, s->buf[s->parity][0], s->buf[s->parity][1], s->n, s->ws,
-                                          s->stream);
-    if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
-    double r[9];
-    e = hipMemcpyAsync(r, (char *)s->ws + gs::diag_result_offset(), sizeof r, hipMemcpyDeviceToHost, s->stream);
-    if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
-    e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_fail(e, "diagnostics sync");
-    out->sum_u = r[0] + r[1];
-    out->sum_v = r[2] + r[3];
-    out->min_u = r[4];
-    out->max_u = r[5];
-    out->min_v = r[6];
-    out->max_v = r[7];
-    out->nonfinite = (int64_t)r[8];
-    if (out->nonfinite > 0) return fail(GS_ERR_NONFINITE, "%lld non-finite values", (long long)out->nonfinite);
-    return GS_OK;
+    return diagnostics(s->p.storage, s->buf[s->parity][0], s->buf[s->parity][1], s->n, s->ws, s->stream, out);
 }
 
 gs_status gs_sync(gs_sim *s)

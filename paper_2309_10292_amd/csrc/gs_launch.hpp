@@ -79,4 +79,32 @@ int num_tb_shapes();
 TileShape tb_shape(int shape, int T);
 hipError_t launch_tblock(int storage, int T, int shape, const void *u, const void *v, void *un, void *vn,
                          const StepArgs &a, hipStream_t st);
+
+// Batched sweep over independent simulations (device tables).
+struct SimDesc {
+    void *buf[2][2];    // [parity][field] device buffers
+    int nx, ny, nz, zc;
+    double F, FK;       // per-simulation feed and F + k
+    float F_f, FK_f;
+    uint64_t seed;
+};
+
+struct WorkItem {
+    int sim, bx, by, bz;
+};
+
+struct BatchArgs {
+    StepArgs coef;       // shared coefficients (Du, Dv, dt, noise); per-sim fields overwritten
+    const SimDesc *sims;
+    const WorkItem *items;
+    int n_items;
+    int parity;          // buffers holding the current state of every simulation of this launch
+    uint64_t t;          // step index of the first fused step (offset when t_dev is set)
+    const uint64_t *t_dev;
+};
+
+hipError_t launch_tblock_batch(int storage, int T, int shape, const BatchArgs &b, int grid, hipStream_t st);
+int tb_shape_lanes(int shape);
+// Resident workgroups per CU of the batched kernel (at least 1).
+int tb_batch_occupancy(int storage, int T, int shape);
 } // namespace gs

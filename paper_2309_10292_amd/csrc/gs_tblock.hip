@@ -90,24 +90,19 @@ __device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu,
     vo = vc + dv * dt;
 }
 
+// One output tile [x0, x0 + 4 TXG) x [y0, y0 + TY) x [z0, ze) of a grid
+// (a.nx, a.ny, a.nz), T steps from (u, v) into (un, vn); t0 is the step index
+// of the first of the T steps. `lds` holds 2 * TbGeom::FIELD elements. Every
+// lane of the workgroup must call it (it contains barriers).
 template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
-__global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const S *__restrict__ v,
-                                                 S *__restrict__ un, S *__restrict__ vn, StepArgs a)
+__device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__restrict__ v, S *__restrict__ un,
+                                        S *__restrict__ vn, const StepArgs &a, int x0, int y0, int z0, int ze,
+                                        uint64_t t0, typename Traits<S>::C *__restrict__ lds)
 {
     typedef TbGeom<S, TXG, TY, T, NT> G;
     typedef typename G::C C;
-    __shared__ C lds[2 * G::FIELD];
-
-    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int bx = (int)(lb % (uint32_t)a.ntx);
-    const uint32_t rest = lb / (uint32_t)a.ntx;
-    const int by = (int)(rest % (uint32_t)a.nty);
-    const int bz = (int)(rest / (uint32_t)a.nty);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int x0 = bx * (TXG * 4), y0 = by * TY, z0 = bz * a.zc;
-    const int ze = min(z0 + a.zc, nz);
     const size_t plane = (size_t)nx * (size_t)ny;
-    const uint64_t t0 = NOISE ? step_index(a) : 0;
 
     // This lane's position: x-group gxs, level-0 row rys.
     const int s = threadIdx.x;
@@ -274,6 +269,54 @@ __global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const 
     }
 }
 
+template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
+__global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const S *__restrict__ v,
+                                                 S *__restrict__ un, S *__restrict__ vn, StepArgs a)
+{
+    typedef TbGeom<S, TXG, TY, T, NT> G;
+    __shared__ typename G::C lds[2 * G::FIELD];
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % (uint32_t)a.ntx);
+    const uint32_t rest = lb / (uint32_t)a.ntx;
+    const int by = (int)(rest % (uint32_t)a.nty);
+    const int bz = (int)(rest / (uint32_t)a.nty);
+    const int z0 = bz * a.zc;
+    const uint64_t t0 = NOISE ? step_index(a) : 0;
+    tb_tile<S, TXG, TY, T, NT, NOISE>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, min(z0 + a.zc, a.nz), t0, lds);
+}
+
+// Persistent sweep over many independent simulations: each workgroup walks
+// the work list (items sorted by decreasing cost) with a stride of the grid
+// size; an item is one tile x z-chunk of one simulation.
+template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
+__global__ __launch_bounds__(NT) void stencil_tb_batch(BatchArgs b)
+{
+    typedef TbGeom<S, TXG, TY, T, NT> G;
+    __shared__ typename G::C lds[2 * G::FIELD];
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint64_t t0 = NOISE ? (b.t_dev ? *b.t_dev + b.t : b.t) : 0;
+    for (uint32_t it = lb; it < (uint32_t)b.n_items; it += gridDim.x) {
+        const WorkItem w = b.items[it];
+        const SimDesc &d = b.sims[w.sim];
+        StepArgs a = b.coef;
+        a.nx = d.nx;
+        a.ny = d.ny;
+        a.nz = d.nz;
+        a.F = d.F;
+        a.FK = d.FK;
+        a.F_f = d.F_f;
+        a.FK_f = d.FK_f;
+        a.seed = d.seed;
+        const int z0 = w.bz * d.zc;
+        const S *u = (const S *)d.buf[b.parity][0];
+        const S *v = (const S *)d.buf[b.parity][1];
+        S *un = (S *)d.buf[b.parity ^ 1][0];
+        S *vn = (S *)d.buf[b.parity ^ 1][1];
+        tb_tile<S, TXG, TY, T, NT, NOISE>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, min(z0 + d.zc, d.nz), t0,
+                                          lds);
+    }
+}
+
 // ------------------------------------------------------------------ launch
 template <typename S, int TXG, int TY, int T, int NT>
 static hipError_t launch_tb_t(const void *u, const void *v, void *un, void *vn, StepArgs a, hipStream_t st)
@@ -332,6 +375,96 @@ TileShape tb_shape(int shape, int T)
     case 3: return TileShape{128, 14 - 2 * T};
     }
     return TileShape{0, 0};
+}
+
+template <typename S, int TXG, int TY, int T, int NT>
+static hipError_t launch_tb_batch_t(const BatchArgs &b, int grid, hipStream_t st)
+{
+    if (grid < 1) return hipErrorInvalidConfiguration;
+    if (b.coef.noise != 0.0)
+        hipLaunchKernelGGL((stencil_tb_batch<S, TXG, TY, T, NT, true>), dim3(grid), dim3(NT), 0, st, b);
+    else
+        hipLaunchKernelGGL((stencil_tb_batch<S, TXG, TY, T, NT, false>), dim3(grid), dim3(NT), 0, st, b);
+    return hipGetLastError();
+}
+
+template <typename S, int T>
+static hipError_t batch_shape(int shape, const BatchArgs &b, int grid, hipStream_t st)
+{
+    switch (shape) {
+    case 1: return launch_tb_batch_t<S, 16, 14 - 2 * T, T, 256>(b, grid, st);
+    case 2: return launch_tb_batch_t<S, 16, 28 - 2 * T, T, 512>(b, grid, st);
+    case 3: return launch_tb_batch_t<S, 32, 14 - 2 * T, T, 512>(b, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename S>
+static hipError_t batch_T(int T, int shape, const BatchArgs &b, int grid, hipStream_t st)
+{
+    switch (T) {
+    case 1: return batch_shape<S, 1>(shape, b, grid, st);
+    case 2: return batch_shape<S, 2>(shape, b, grid, st);
+    case 3: return batch_shape<S, 3>(shape, b, grid, st);
+    case 4: return batch_shape<S, 4>(shape, b, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tblock_batch(int storage, int T, int shape, const BatchArgs &b, int grid, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return batch_T<double>(T, shape, b, grid, st);
+    case 1: return batch_T<float>(T, shape, b, grid, st);
+    case 2: return batch_T<bf16>(T, shape, b, grid, st);
+    case 3: return batch_T<f16>(T, shape, b, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int tb_shape_lanes(int shape) { return shape == 1 ? 256 : 512; }
+
+template <typename S, int TXG, int TY, int T, int NT>
+static int occ_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stencil_tb_batch<S, TXG, TY, T, NT, false>, NT, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <typename S, int T>
+static int occ_shape(int shape)
+{
+    switch (shape) {
+    case 1: return occ_t<S, 16, 14 - 2 * T, T, 256>();
+    case 2: return occ_t<S, 16, 28 - 2 * T, T, 512>();
+    case 3: return occ_t<S, 32, 14 - 2 * T, T, 512>();
+    }
+    return 1;
+}
+
+template <typename S>
+static int occ_T(int T, int shape)
+{
+    switch (T) {
+    case 1: return occ_shape<S, 1>(shape);
+    case 2: return occ_shape<S, 2>(shape);
+    case 3: return occ_shape<S, 3>(shape);
+    case 4: return occ_shape<S, 4>(shape);
+    }
+    return 1;
+}
+
+int tb_batch_occupancy(int storage, int T, int shape)
+{
+    switch (storage) {
+    case 0: return occ_T<double>(T, shape);
+    case 1: return occ_T<float>(T, shape);
+    case 2: return occ_T<bf16>(T, shape);
+    case 3: return occ_T<f16>(T, shape);
+    }
+    return 1;
 }
 
 hipError_t launch_tblock(int storage, int T, int shape, const void *u, const void *v, void *un, void *vn,

@@ -47,6 +47,12 @@ class gs_tune_entry(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
+class gs_batch_tune_entry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("n_sims", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("tblock", ctypes.c_int32), ("zchunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("ms_per_step", ctypes.c_double), ("gcells", ctypes.c_double)]
+
+
 class GSError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -77,6 +83,21 @@ SIGNATURES = [
     ("gs_get_config", _I32, [_SIM, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("gs_tune", _I32, [_SIM, _I32, ctypes.c_void_p, _I32, ctypes.POINTER(_I32)]),
     ("gs_step_graph", _I32, [_SIM, _I64]),
+    ("gs_batch_arena_bytes", _SZ, [_I32, _I32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("gs_batch_workspace_bytes", _SZ, [_I32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("gs_batch_init", _I32, [_PP, _I32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p, _VP, _SZ, _VP, _SZ, _VP, ctypes.POINTER(_SIM)]),
+    ("gs_batch_step", _I32, [_SIM, _I64]),
+    ("gs_batch_step_graph", _I32, [_SIM, _I64]),
+    ("gs_batch_set_config", _I32, [_SIM, _I32, _I32, _I32, _I32]),
+    ("gs_batch_get_config", _I32, [_SIM, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("gs_batch_tune", _I32, [_SIM, _I32, ctypes.c_void_p, _I32, ctypes.POINTER(_I32)]),
+    ("gs_batch_current", _I32, [_SIM, _I32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_uint64)]),
+    ("gs_batch_read", _I32, [_SIM, _I32, _DP, _DP]),
+    ("gs_batch_write", _I32, [_SIM, _I32, _DP, _DP]),
+    ("gs_batch_diagnostics", _I32, [_SIM, _I32, ctypes.POINTER(gs_diag)]),
+    ("gs_batch_sync", _I32, [_SIM]),
+    ("gs_batch_destroy", _I32, [_SIM]),
     ("gs_laplacian7", _I32, [_VP, _VP, _I32, _I32, _I32, _VP]),
     ("gs_copy", _I32, [_VP, _VP, _SZ, _VP]),
 ]
@@ -232,6 +253,105 @@ class Sim:
     def close(self):
         if self.h is not None and self.h.value:
             check(load().gs_destroy(self.h))
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Many independent simulations advanced by persistent launches.
+
+    `sims` is a list of dicts {nx, ny, nz, F, k} (or {L, F, k} for cubes);
+    the remaining keyword arguments are the shared gs_params (storage, Du, Dv,
+    dt, noise, seed, init, cube_side, ...). One torch allocation holds all
+    fields (the arena) and one the workspace.
+    """
+
+    def __init__(self, sims, *, device="cuda", stream=None, **kw):
+        import torch
+        lib = load()
+        n = len(sims)
+        dims = [(int(d.get("nx", d.get("L"))), int(d.get("ny", d.get("L"))), int(d.get("nz", d.get("L"))))
+                for d in sims]
+        self.n = n
+        self.shapes = [(nz, ny, nx) for (nx, ny, nz) in dims]
+        self.nx = (ctypes.c_int32 * n)(*[d[0] for d in dims])
+        self.ny = (ctypes.c_int32 * n)(*[d[1] for d in dims])
+        self.nz = (ctypes.c_int32 * n)(*[d[2] for d in dims])
+        F = (ctypes.c_double * n)(*[float(d["F"]) for d in sims])
+        k = (ctypes.c_double * n)(*[float(d["k"]) for d in sims])
+        self.params = make_params(8, 8, 8, **kw)
+        arena_b = int(lib.gs_batch_arena_bytes(self.params.storage, n, self.nx, self.ny, self.nz))
+        ws_b = int(lib.gs_batch_workspace_bytes(n, self.nx, self.ny, self.nz))
+        if arena_b == 0 or ws_b == 0:
+            raise GSError(GS_ERR_INVALID_ARG, "invalid batch grid sizes or storage type")
+        dev = torch.device(device)
+        self.arena = torch.empty(arena_b, dtype=torch.uint8, device=dev)
+        self.workspace = torch.empty(ws_b, dtype=torch.uint8, device=dev)
+        self.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        check(lib.gs_batch_init(ctypes.byref(self.params), n, self.nx, self.ny, self.nz, F, k,
+                                self.arena.data_ptr(), arena_b, self.workspace.data_ptr(), ws_b, self.stream,
+                                ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n: int = 1):
+        check(load().gs_batch_step(self.h, int(n)))
+
+    def step_graph(self, n: int):
+        check(load().gs_batch_step_graph(self.h, int(n)))
+
+    def set_config(self, tile, tblock, zchunk, sim=-1):
+        check(load().gs_batch_set_config(self.h, int(sim), int(tile), int(tblock), int(zchunk)))
+
+    def config(self, sim):
+        t, b, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(load().gs_batch_get_config(self.h, int(sim), ctypes.byref(t), ctypes.byref(b), ctypes.byref(z)))
+        return dict(tile=t.value, tblock=b.value, zchunk=z.value)
+
+    def tune(self, reps: int = 2):
+        cap = 1024
+        table = (gs_batch_tune_entry * cap)()
+        n = ctypes.c_int32()
+        check(load().gs_batch_tune(self.h, int(reps), ctypes.cast(table, ctypes.c_void_p), cap, ctypes.byref(n)))
+        return [dict(nx=e.nx, ny=e.ny, nz=e.nz, n_sims=e.n_sims, tile=e.tile, tblock=e.tblock, zchunk=e.zchunk,
+                     ms_per_step=e.ms_per_step, gcells=e.gcells) for e in table[:min(n.value, cap)]]
+
+    def current_ptrs(self, sim):
+        pu, pv, st = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_uint64()
+        check(load().gs_batch_current(self.h, int(sim), ctypes.byref(pu), ctypes.byref(pv), ctypes.byref(st)))
+        return pu.value, pv.value, int(st.value)
+
+    def read(self, sim):
+        shape = self.shapes[sim]
+        u = np.empty(shape, dtype=np.float64)
+        v = np.empty(shape, dtype=np.float64)
+        check(load().gs_batch_read(self.h, int(sim), u.ctypes.data_as(_DP), v.ctypes.data_as(_DP)))
+        return u, v
+
+    def write(self, sim, u, v):
+        shape = self.shapes[sim]
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert u.shape == shape and v.shape == shape
+        check(load().gs_batch_write(self.h, int(sim), u.ctypes.data_as(_DP), v.ctypes.data_as(_DP)))
+
+    def diagnostics(self, sim):
+        d = gs_diag()
+        check(load().gs_batch_diagnostics(self.h, int(sim), ctypes.byref(d)))
+        return dict(sum_u=d.sum_u, sum_v=d.sum_v, min_u=d.min_u, max_u=d.max_u, min_v=d.min_v,
+                    max_v=d.max_v, nonfinite=int(d.nonfinite))
+
+    def sync(self):
+        check(load().gs_batch_sync(self.h))
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            check(load().gs_batch_destroy(self.h))
         self.h = None
 
     def __enter__(self):
