@@ -71,13 +71,29 @@ def time_steps(torch, sim, steps, warmup):
     return total / steps, per_launch, full // T
 
 
+KERNEL_SOURCES = ["paper_2309_10292_amd/csrc/gs_tblock.hip", "paper_2309_10292_amd/csrc/gs_device.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_for(path, kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), or
+    None when there is no measurement or the kernel sources changed since."""
     try:
         with open(path) as f:
-            t = json.load(f)
-        return t.get(kernel_key)
+            t = json.load(f).get(kernel_key)
     except (OSError, ValueError):
         return None
+    if not t or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t["bytes"]
 
 
 def cpu_baseline(L, p, budget_s):

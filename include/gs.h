@@ -243,6 +243,54 @@ gs_status gs_batch_sync(gs_batch *b);
 gs_status gs_batch_destroy(gs_batch *b);
 
 /* ------------------------------------------------------------------ */
+/* Learned surrogate of 16 steps: a network of four circular 3x3x3
+ * convolutions (channels 4 -> 32 -> 32 -> 32 -> 2, GELU after the first
+ * three, bias everywhere) mapping (u, v, (F - 0.035) / 0.025, (k - 0.055) /
+ * 0.015) to a correction added to (u, v). BF16 weights and activations, FP32
+ * accumulation on the matrix cores, FP32 master weights for Adam.
+ * Parameters are a flat FP32 host array of GS_SURR_NPARAMS values: for each
+ * layer W[c_out][c_in][3][3][3] (row-major; W[o][i][dz][dy][dx] multiplies
+ * the input at (z + dz - 1, y + dy - 1, x + dx - 1), periodic), then b[c_out].
+ * Fields are planar device arrays, sample-major: nsamp * nx * ny * nz values,
+ * x fastest. Grids need nx % 16 == 0 and a cell count divisible by 32. */
+
+#define GS_SURR_NPARAMS 60578
+
+typedef struct gs_surrogate gs_surrogate;
+
+size_t gs_surrogate_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t max_batch);
+
+/* Binds a caller-owned workspace for batches of up to max_batch samples and
+ * uploads `params` (synchronising). */
+gs_status gs_surrogate_init(int32_t nx, int32_t ny, int32_t nz, int32_t max_batch, const float *params,
+                            void *workspace, size_t workspace_bytes, void *hip_stream, gs_surrogate **out);
+
+/* Replaces the parameters (and resets the Adam moments), or reads them back.
+ * Both synchronise. */
+gs_status gs_surrogate_set_params(gs_surrogate *s, const float *params);
+gs_status gs_surrogate_get_params(gs_surrogate *s, float *params);
+
+/* Prediction of nsamp <= max_batch samples; io_storage is GS_F64 or GS_F32
+ * for u, v, u_out, v_out (device, must not alias); F and k are host arrays of
+ * nsamp values. Asynchronous after the upload of F and k. */
+gs_status gs_surrogate_predict(gs_surrogate *s, int32_t nsamp, int32_t io_storage, const void *u, const void *v,
+                               const double *F, const double *k, void *u_out, void *v_out);
+
+/* Mean squared error of the prediction against (u_target, v_target) over all
+ * samples, both fields and all cells (FP32 device inputs), and its gradient
+ * with respect to every parameter, kept on the device for gs_surrogate_adam
+ * and copied to grad_host (GS_SURR_NPARAMS floats) when it is non-NULL.
+ * Synchronising; *loss receives the loss. */
+gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u, const float *v,
+                                 const float *u_target, const float *v_target, const double *F, const double *k,
+                                 double *loss, float *grad_host);
+
+/* One Adam step with the last gradient (bias-corrected moments). */
+gs_status gs_surrogate_adam(gs_surrogate *s, float lr, float beta1, float beta2, float eps);
+
+gs_status gs_surrogate_destroy(gs_surrogate *s);
+
+/* ------------------------------------------------------------------ */
 /* Calibration kernels (measure the single-field stencil and plain streaming
  * on the same device, the analogue of the paper's Table 2 / Table 3 rows). */
 

@@ -1,0 +1,418 @@
+// Learned 16-step surrogate: a 4-layer 3x3x3 circular convolution network
+// (channels 4 -> 32 -> 32 -> 32 -> 2, GELU, residual output) on gfx950 with
+// BF16 weights and activations and FP32 accumulation on the matrix cores.
+//
+// Activations are channels-last (cell-major, channels contiguous: 8 channels
+// for the input layer, 32 for hidden layers), so one lane's K fragment of an
+// implicit GEMM (8 consecutive channels of one neighbour cell) is one 16-byte
+// load. Convolutions are implicit GEMMs with M = cells (tiles of 16 cells of
+// one x-row), N = output channels (tiles of 16) and K = 27 offsets x input
+// channels, walked in chunks of 32 with v_mfma_f32_16x16x32_bf16; the packed
+// weights of a layer sit in LDS. The data gradient is the same convolution
+// with the weights transposed and the offsets mirrored; the weight gradient
+// is a GEMM with K = cells, reduced per workgroup into FP32 partials.
+#include "gs_device.hpp"
+#include "gs_surrogate.hpp"
+
+namespace gs {
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ u16 f2bf(float f) { return bf16_rne(f).bits; }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ bf16x8 load8(const u16 *p)
+{
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    return __builtin_bit_cast(bf16x8, q);
+}
+
+// Row index (sample * ncell + cell) of the neighbour at offset d of a cell.
+__device__ __forceinline__ size_t nbr_row(const Geo &g, int s, int x, int y, int z, int d)
+{
+    const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
+    const int xn = wrapc(x + dx - 1, g.nx), yn = wrapc(y + dy - 1, g.ny), zn = wrapc(z + dz - 1, g.nz);
+    return (size_t)s * g.ncell + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * zn);
+}
+
+// ------------------------------------------------------------------ convolution
+// MODE_HIDDEN: z = acc + bias, writes z and GELU(z) (32 channels, BF16).
+// MODE_OUT:    pred = residual input + acc + bias for output channels 0, 1.
+// MODE_DGRAD:  writes acc * GELU'(zprev) (the gradient of the layer below's
+//              pre-activation, 32 channels, BF16).
+template <int CIN, int NT, int MODE, typename IO>
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
+{
+    constexpr int NCH = (27 * CIN + 31) / 32;
+    __shared__ uint4 wl[NCH * NT * 64];
+    const uint4 *wg = reinterpret_cast<const uint4 *>(a.wpack);
+    for (int i = threadIdx.x; i < NCH * NT * 64; i += 256) wl[i] = wg[i];
+    __syncthreads();
+
+    const Geo g = a.geo;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, quad = lane >> 4;
+    const size_t rows = (size_t)a.nsamp * g.ncell;
+    const size_t n_mt = rows / 16;
+    for (size_t mt = (size_t)blockIdx.x * 4 + wave; mt < n_mt; mt += (size_t)gridDim.x * 4) {
+        const size_t row0 = mt * 16;
+        const int s = (int)(row0 / g.ncell);
+        const int c0 = (int)(row0 % g.ncell);
+        const int x0 = c0 % g.nx, y = (c0 / g.nx) % g.ny, z = c0 / (g.nx * g.ny);
+        f32x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 9
+        for (int c = 0; c < NCH; ++c) {
+            const int k0 = 32 * c + 8 * quad;
+            const int d = k0 / CIN, ci0 = k0 % CIN;
+            bf16x8 av;
+            if (d < 27) {
+                av = load8(a.in + nbr_row(g, s, x0 + col, y, z, d) * CIN + ci0);
+            } else {
+                av = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+        // acc[t][j]: cell c0 + 4 quad + j, output channel 16 t + col.
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = 16 * t + col;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const size_t r = row0 + 4 * quad + j;
+                const float v = acc[t][j];
+                if constexpr (MODE == MODE_HIDDEN) {
+                    const float zz = v + a.bias[co];
+                    a.zout[r * 32 + co] = f2bf(zz);
+                    a.aout[r * 32 + co] = f2bf(gelu(zz));
+                } else if constexpr (MODE == MODE_OUT) {
+                    if (co < 2) {
+                        // r = s * ncell + cell indexes the planar (sample, cell) fields
+                        const IO *res = co == 0 ? (const IO *)a.res_u : (const IO *)a.res_v;
+                        IO *out = co == 0 ? (IO *)a.out_u : (IO *)a.out_v;
+                        out[r] = res[r] + (IO)(v + a.bias[co]);
+                    }
+                } else {
+                    const float zp = bf2f(a.zprev[r * 32 + co]);
+                    a.aout[r * 32 + co] = f2bf(v * gelu_grad(zp));
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weight gradient
+// dW[d][co][ci] = sum over cells of dz[cell][co] * act[neighbour(cell, d)][ci].
+// A = dz^T (rows co, K = cells), B = act (K = cells, columns ci). Wave w
+// handles offsets d = w, w + 4, ...; each workgroup walks chunks of 32 cells
+// and writes its partial sums (padded 16*MT x 16*NT per offset).
+template <int CIN, int COUTS, int MT, int NT>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
+{
+    constexpr int ND = 7; // ceil(27 / 4)
+    const Geo g = a.geo;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15, quad = lane >> 4;
+    f32x4 acc[ND][MT][NT];
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[i][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const size_t rows = (size_t)a.nsamp * g.ncell;
+    const size_t n_kc = rows / 32;
+    for (size_t kc = blockIdx.x; kc < n_kc; kc += gridDim.x) {
+        const size_t r0 = kc * 32 + 8 * quad; // this lane's 8 cells: r0 .. r0 + 7 (one x-row)
+        const int s = (int)(r0 / g.ncell);
+        const int c0 = (int)(r0 % g.ncell);
+        const int x0 = c0 % g.nx, y = (c0 / g.nx) % g.ny, z = c0 / (g.nx * g.ny);
+        bf16x8 av[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int co = 16 * m + col;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const u16 b = co < COUTS ? a.dz[(r0 + j) * COUTS + co] : (u16)0;
+                av[m][j] = __builtin_bit_cast(__bf16, b);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+            const int d = wave + 4 * i;
+            if (d >= 27) break;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int ci = 16 * n + col;
+                bf16x8 bv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const u16 b = ci < CIN ? a.act[nbr_row(g, s, x0 + j, y, z, d) * CIN + ci] : (u16)0;
+                    bv[j] = __builtin_bit_cast(__bf16, b);
+                }
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    acc[i][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[i][m][n], 0, 0, 0);
+            }
+        }
+    }
+    // acc[i][m][n][j]: offset d, co = 16 m + 4 quad + j, ci = 16 n + col.
+    constexpr int PCO = 16 * MT, PCI = 16 * NT;
+    float *part = a.part + (size_t)blockIdx.x * 27 * PCO * PCI;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+        const int d = wave + 4 * i;
+        if (d >= 27) break;
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    part[((size_t)d * PCO + 16 * m + 4 * quad + j) * PCI + 16 * n + col] = acc[i][m][n][j];
+    }
+}
+
+// grad[W(co, ci, d)] = sum over workgroups of the partials (fixed order).
+__global__ __launch_bounds__(256) void wgrad_reduce(const float *__restrict__ part, int nblk, int pco, int pci,
+                                                    int cout, int cin, float *__restrict__ gW)
+{
+    const int n = cout * cin * 27;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int d = e % 27, ci = (e / 27) % cin, co = e / (27 * cin);
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(((size_t)b * 27 + d) * pco + co) * pci + ci];
+        gW[e] = (float)s;
+    }
+}
+
+// Bias gradient: per-workgroup channel sums of dz, then a fixed-order fold.
+__global__ __launch_bounds__(256) void colsum_partial(const u16 *__restrict__ dz, size_t rows, int cs, int cout,
+                                                      float *__restrict__ part)
+{
+    __shared__ float red[256];
+    const int c = threadIdx.x % 32, r = threadIdx.x / 32; // 8 row lanes x 32 channels
+    float acc = 0.f;
+    if (c < cout)
+        for (size_t row = (size_t)blockIdx.x * 8 + r; row < rows; row += (size_t)gridDim.x * 8) acc += bf2f(dz[row * cs + c]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (r == 0 && c < cout) {
+        float t = 0.f;
+        for (int i = 0; i < 8; ++i) t += red[i * 32 + c];
+        part[(size_t)blockIdx.x * 32 + c] = t;
+    }
+}
+
+__global__ __launch_bounds__(64) void colsum_reduce(const float *__restrict__ part, int nblk, int cout,
+                                                    float *__restrict__ gb)
+{
+    const int c = threadIdx.x;
+    if (c >= cout) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 32 + c];
+    gb[c] = (float)s;
+}
+
+// ------------------------------------------------------------------ input, loss, optimiser
+template <typename IO>
+__global__ __launch_bounds__(256) void pack_input(const IO *__restrict__ u, const IO *__restrict__ v,
+                                                  const float *__restrict__ fk, int nsamp, int ncell,
+                                                  u16 *__restrict__ x)
+{
+    const size_t rows = (size_t)nsamp * ncell;
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(r / ncell);
+        uint4 q;
+        q.x = (uint32_t)f2bf((float)u[r]) | ((uint32_t)f2bf((float)v[r]) << 16);
+        q.y = (uint32_t)f2bf((fk[2 * s] - F_CENTER) / F_SCALE) | ((uint32_t)f2bf((fk[2 * s + 1] - K_CENTER) / K_SCALE) << 16);
+        q.z = 0u;
+        q.w = 0u;
+        *reinterpret_cast<uint4 *>(x + r * 8) = q;
+    }
+}
+
+// Residuals of the prediction, their squared sum per workgroup, and the loss
+// gradient dL/dpred = 2 (pred - target) / n_terms (channels 0, 1 of 8).
+__global__ __launch_bounds__(256) void loss_grad(const float *__restrict__ pu, const float *__restrict__ pv,
+                                                 const float *__restrict__ tu, const float *__restrict__ tv,
+                                                 size_t rows, float scale, u16 *__restrict__ dz4,
+                                                 double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (size_t)gridDim.x * blockDim.x) {
+        const float ru = pu[r] - tu[r], rv = pv[r] - tv[r];
+        acc += (double)ru * ru + (double)rv * rv;
+        uint4 q;
+        q.x = (uint32_t)f2bf(scale * ru) | ((uint32_t)f2bf(scale * rv) << 16);
+        q.y = q.z = q.w = 0u;
+        *reinterpret_cast<uint4 *>(dz4 + r * 8) = q;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const float *__restrict__ gr,
+                                                   float *__restrict__ m, float *__restrict__ v, int n, float lr,
+                                                   float b1, float b2, float eps, float c1, float c2)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float g = gr[i];
+        const float mi = b1 * m[i] + (1.f - b1) * g;
+        const float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Packs layer weights (FP32, W[co][ci][d]) into the B-fragment order of the
+// convolution kernel: chunk c, N-tile t, lane, 8 consecutive k = 32 c + 8
+// (lane / 16) + j with k = d * cins + ci. DGRAD packs the mirrored, transposed
+// weights W'[ci][co][d] = W[co][ci][26 - d] (input channels = co).
+__global__ __launch_bounds__(256) void repack(const float *__restrict__ W, int cout, int cin, int cins, int nt,
+                                              int nch, int dgrad, u16 *__restrict__ out)
+{
+    const int total = nch * nt * 64 * 8;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int j = e % 8, lane = (e / 8) % 64, t = (e / 512) % nt, c = e / (512 * nt);
+        const int k = 32 * c + 8 * (lane / 16) + j;
+        const int d = k / cins, kc = k % cins, n = 16 * t + lane % 16;
+        float w = 0.f;
+        if (d < 27) {
+            if (!dgrad) {
+                if (kc < cin && n < cout) w = W[((size_t)n * cin + kc) * 27 + d];
+            } else {
+                // input channel kc = co of the layer, output channel n = ci of the layer
+                if (kc < cout && n < cin) w = W[((size_t)kc * cin + n) * 27 + (26 - d)];
+            }
+        }
+        out[e] = f2bf(w);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_cap(size_t work, int per_block, int cap)
+{
+    size_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > (size_t)cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a, hipStream_t st)
+{
+    const size_t mts = (size_t)a.nsamp * a.geo.ncell / 16;
+    const int grid = grid_cap(mts, 4, 256 * 16);
+#define GS_CONV(CI, N, M, IO) hipLaunchKernelGGL((conv_kernel<CI, N, M, IO>), dim3(grid), dim3(256), 0, st, a)
+    if (cin == 8 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(8, 2, MODE_HIDDEN, float);
+    else if (cin == 32 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(32, 2, MODE_HIDDEN, float);
+    else if (cin == 32 && nt == 1 && mode == MODE_OUT && io_f64) GS_CONV(32, 1, MODE_OUT, double);
+    else if (cin == 32 && nt == 1 && mode == MODE_OUT) GS_CONV(32, 1, MODE_OUT, float);
+    else if (cin == 8 && nt == 2 && mode == MODE_DGRAD) GS_CONV(8, 2, MODE_DGRAD, float);
+    else if (cin == 32 && nt == 2 && mode == MODE_DGRAD) GS_CONV(32, 2, MODE_DGRAD, float);
+    else return hipErrorInvalidValue;
+#undef GS_CONV
+    return hipGetLastError();
+}
+
+int wgrad_blocks() { return 256; }
+
+hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st)
+{
+    const int grid = wgrad_blocks();
+    if (cin == 32 && couts == 32)
+        hipLaunchKernelGGL((wgrad_kernel<32, 32, 2, 2>), dim3(grid), dim3(256), 0, st, a);
+    else if (cin == 32 && couts == 8)
+        hipLaunchKernelGGL((wgrad_kernel<32, 8, 1, 2>), dim3(grid), dim3(256), 0, st, a);
+    else if (cin == 8 && couts == 32)
+        hipLaunchKernelGGL((wgrad_kernel<8, 32, 2, 1>), dim3(grid), dim3(256), 0, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, float *gW, hipStream_t st)
+{
+    const int n = cout * cin * 27;
+    hipLaunchKernelGGL(wgrad_reduce, dim3(grid_cap(n, 256, 1024)), dim3(256), 0, st, part, wgrad_blocks(), pco, pci,
+                       cout, cin, gW);
+    return hipGetLastError();
+}
+
+int colsum_blocks() { return 512; }
+
+hipError_t launch_bias_grad(const uint16_t *dz, size_t rows, int cs, int cout, float *part, float *gb, hipStream_t st)
+{
+    hipLaunchKernelGGL(colsum_partial, dim3(colsum_blocks()), dim3(256), 0, st, dz, rows, cs, cout, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_reduce, dim3(1), dim3(64), 0, st, (const float *)part, colsum_blocks(), cout, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(int io_f64, const void *u, const void *v, const float *fk, int nsamp, int ncell,
+                             uint16_t *x, hipStream_t st)
+{
+    const int grid = grid_cap((size_t)nsamp * ncell, 256, 65536);
+    if (io_f64)
+        hipLaunchKernelGGL(pack_input<double>, dim3(grid), dim3(256), 0, st, (const double *)u, (const double *)v, fk,
+                           nsamp, ncell, x);
+    else
+        hipLaunchKernelGGL(pack_input<float>, dim3(grid), dim3(256), 0, st, (const float *)u, (const float *)v, fk,
+                           nsamp, ncell, x);
+    return hipGetLastError();
+}
+
+int loss_blocks() { return 1024; }
+
+hipError_t launch_loss_grad(const float *pu, const float *pv, const float *tu, const float *tv, size_t rows,
+                            float scale, uint16_t *dz4, double *part, hipStream_t st)
+{
+    hipLaunchKernelGGL(loss_grad, dim3(loss_blocks()), dim3(256), 0, st, pu, pv, tu, tv, rows, scale, dz4, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_cap(n, 256, 1024)), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_repack(const float *W, int cout, int cin, int cins, int nt, int nch, int dgrad, uint16_t *out,
+                         hipStream_t st)
+{
+    const int total = nch * nt * 512;
+    hipLaunchKernelGGL(repack, dim3(grid_cap(total, 256, 1024)), dim3(256), 0, st, W, cout, cin, cins, nt, nch, dgrad,
+                       out);
+    return hipGetLastError();
+}
+
+} // namespace nn
+} // namespace gs

@@ -98,6 +98,15 @@ SIGNATURES = [
     ("gs_batch_diagnostics", _I32, [_SIM, _I32, ctypes.POINTER(gs_diag)]),
     ("gs_batch_sync", _I32, [_SIM]),
     ("gs_batch_destroy", _I32, [_SIM]),
+    ("gs_surrogate_workspace_bytes", _SZ, [_I32, _I32, _I32, _I32]),
+    ("gs_surrogate_init", _I32, [_I32, _I32, _I32, _I32, ctypes.c_void_p, _VP, _SZ, _VP, ctypes.POINTER(_SIM)]),
+    ("gs_surrogate_set_params", _I32, [_SIM, ctypes.c_void_p]),
+    ("gs_surrogate_get_params", _I32, [_SIM, ctypes.c_void_p]),
+    ("gs_surrogate_predict", _I32, [_SIM, _I32, _I32, _VP, _VP, ctypes.c_void_p, ctypes.c_void_p, _VP, _VP]),
+    ("gs_surrogate_loss_grad", _I32, [_SIM, _I32, _VP, _VP, _VP, _VP, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    ("gs_surrogate_adam", _I32, [_SIM, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    ("gs_surrogate_destroy", _I32, [_SIM]),
     ("gs_laplacian7", _I32, [_VP, _VP, _I32, _I32, _I32, _VP]),
     ("gs_copy", _I32, [_VP, _VP, _SZ, _VP]),
 ]
