@@ -145,6 +145,23 @@ gs_status gs_current(gs_sim *s, void **u_dev, void **v_dev, uint64_t *step);
  * state. Returns GS_ERR_NONFINITE (with *out filled) when nonfinite > 0. */
 gs_status gs_diagnostics(gs_sim *s, gs_diag *out);
 
+/* Sets the global step index of the current state (the noise key of the
+ * next step), for callers that replace the state by other means, such as a
+ * learned surrogate's jump. */
+gs_status gs_set_step(gs_sim *s, uint64_t step);
+
+/* Replaces the current state by u = 1, v = 0 and the periodic cube of side
+ * `side` with lower corner (x0, y0, z0) (wrapping around the grid) set to
+ * (cu, cv). Asynchronous. */
+gs_status gs_fill_cube(gs_sim *s, int32_t x0, int32_t y0, int32_t z0, int32_t side, double cu, double cv);
+
+/* Synchronising: *out = sum over i < n of (a_i - b_i)^2 in FP64 for two
+ * device arrays of the storage type; `workspace` holds
+ * gs_sqdiff_workspace_bytes() device bytes. */
+size_t gs_sqdiff_workspace_bytes(void);
+gs_status gs_sqdiff(const void *a, const void *b, size_t n, int32_t storage, void *workspace, void *hip_stream,
+                    double *out);
+
 /* Waits for all work enqueued by this handle. */
 gs_status gs_sync(gs_sim *s);
 
@@ -238,6 +255,10 @@ gs_status gs_batch_current(gs_batch *b, int32_t sim, void **u_dev, void **v_dev,
 gs_status gs_batch_read(gs_batch *b, int32_t sim, double *u_host, double *v_host);
 gs_status gs_batch_write(gs_batch *b, int32_t sim, const double *u_host, const double *v_host);
 gs_status gs_batch_diagnostics(gs_batch *b, int32_t sim, gs_diag *out);
+
+/* As gs_fill_cube, for one simulation of a batch. */
+gs_status gs_batch_fill_cube(gs_batch *b, int32_t sim, int32_t x0, int32_t y0, int32_t z0, int32_t side, double cu,
+                             double cv);
 
 gs_status gs_batch_sync(gs_batch *b);
 gs_status gs_batch_destroy(gs_batch *b);

@@ -624,6 +624,49 @@ gs_status gs_step_graph(gs_sim *s, int64_t n_steps)
     return GS_OK;
 }
 
+gs_status gs_set_step(gs_sim *s, uint64_t step)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    s->step = step;
+    return GS_OK;
+}
+
+gs_status gs_fill_cube(gs_sim *s, int32_t x0, int32_t y0, int32_t z0, int32_t side, double cu, double cv)
+{
+    gs_status st = check(s);
+    if (st != GS_OK) return st;
+    int mn = s->p.nx < s->p.ny ? s->p.nx : s->p.ny;
+    mn = mn < s->p.nz ? mn : s->p.nz;
+    if (side < 1 || side > mn) return fail(GS_ERR_INVALID_ARG, "side %d outside [1, %d]", side, mn);
+    if (x0 < 0 || y0 < 0 || z0 < 0 || x0 >= s->p.nx || y0 >= s->p.ny || z0 >= s->p.nz)
+        return fail(GS_ERR_INVALID_ARG, "corner outside the grid");
+    if (!std::isfinite(cu) || !std::isfinite(cv)) return fail(GS_ERR_INVALID_ARG, "cube values must be finite");
+    hipError_t e = gs::launch_init_box(s->p.storage, s->buf[s->parity][0], s->buf[s->parity][1], s->p.nx, s->p.ny,
+                                       s->p.nz, x0, y0, z0, side, cu, cv, s->stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "fill kernel launch");
+}
+
+size_t gs_sqdiff_workspace_bytes(void) { return (size_t)gs::sqdiff_blocks() * sizeof(double); }
+
+gs_status gs_sqdiff(const void *a, const void *b, size_t n, int32_t storage, void *workspace, void *hip_stream,
+                    double *out)
+{
+    if (!a || !b || !workspace || !out) return fail(GS_ERR_INVALID_ARG, "NULL pointer");
+    if (storage_bytes(storage) == 0) return fail(GS_ERR_INVALID_ARG, "unknown storage type %d", storage);
+    if (!aligned(workspace, 8)) return fail(GS_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<double> part(gs::sqdiff_blocks());
+    hipError_t e = gs::launch_sqdiff(storage, a, b, n, (double *)workspace, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(part.data(), workspace, part.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "gs_sqdiff");
+    double sum = 0.0;
+    for (double x : part) sum += x;
+    *out = sum;
+    return GS_OK;
+}
+
 gs_status gs_laplacian7(const double *f, double *out, int32_t nx, int32_t ny, int32_t nz, void *hip_stream)
 {
     if (!f || !out) return fail(GS_ERR_INVALID_ARG, "NULL pointer");

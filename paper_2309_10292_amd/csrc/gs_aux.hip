@@ -51,6 +51,76 @@ hipError_t launch_init_cube(int storage, void *u, void *v, int nx, int ny, int n
     return hipGetLastError();
 }
 
+// Periodic box [x0, x0 + side) x [y0, y0 + side) x [z0, z0 + side) (wrapping
+// around the grid) holds (cu, cv); every other cell (1, 0).
+template <typename S>
+__global__ __launch_bounds__(256) void init_box_kernel(S *__restrict__ u, S *__restrict__ v, int nx, int ny, int nz,
+                                                       int x0, int y0, int z0, int side, double cu, double cv)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const size_t r = i / nx;
+        const int y = (int)(r % ny);
+        const int z = (int)(r / ny);
+        const int dx = (x - x0 + nx) % nx, dy = (y - y0 + ny) % ny, dz = (z - z0 + nz) % nz;
+        const bool in = dx < side && dy < side && dz < side;
+        typedef typename Traits<S>::C C;
+        u[i] = Traits<S>::store(in ? (C)cu : (C)1);
+        v[i] = Traits<S>::store(in ? (C)cv : (C)0);
+    }
+}
+
+hipError_t launch_init_box(int storage, void *u, void *v, int nx, int ny, int nz, int x0, int y0, int z0, int side,
+                           double cu, double cv, hipStream_t st)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    const unsigned g = grid_for(n, 256, 65536);
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(init_box_kernel<double>, dim3(g), dim3(256), 0, st, (double *)u, (double *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
+    case 1: hipLaunchKernelGGL(init_box_kernel<float>, dim3(g), dim3(256), 0, st, (float *)u, (float *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
+    case 2: hipLaunchKernelGGL(init_box_kernel<bf16>, dim3(g), dim3(256), 0, st, (bf16 *)u, (bf16 *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
+    case 3: hipLaunchKernelGGL(init_box_kernel<f16>, dim3(g), dim3(256), 0, st, (f16 *)u, (f16 *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Sum over i of (a_i - b_i)^2 in FP64: per-workgroup partials (fixed tree).
+template <typename S>
+__global__ __launch_bounds__(256) void sqdiff_partial(const S *__restrict__ a, const S *__restrict__ b, size_t n,
+                                                      double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double d = (double)Traits<S>::load(a[i]) - (double)Traits<S>::load(b[i]);
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+int sqdiff_blocks() { return 512; }
+
+hipError_t launch_sqdiff(int storage, const void *a, const void *b, size_t n, double *part, hipStream_t st)
+{
+    const unsigned g = sqdiff_blocks();
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(sqdiff_partial<double>, dim3(g), dim3(256), 0, st, (const double *)a, (const double *)b, n, part); break;
+    case 1: hipLaunchKernelGGL(sqdiff_partial<float>, dim3(g), dim3(256), 0, st, (const float *)a, (const float *)b, n, part); break;
+    case 2: hipLaunchKernelGGL(sqdiff_partial<bf16>, dim3(g), dim3(256), 0, st, (const bf16 *)a, (const bf16 *)b, n, part); break;
+    case 3: hipLaunchKernelGGL(sqdiff_partial<f16>, dim3(g), dim3(256), 0, st, (const f16 *)a, (const f16 *)b, n, part); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ diagnostics
 // Neumaier-compensated FP64 accumulation; every reduction tree below has a
 // fixed shape, so results do not depend on scheduling.

@@ -661,6 +661,23 @@ gs_status gs_batch_diagnostics(gs_batch *b, int32_t sim, gs_diag *out)
     return diagnostics(b->base.storage, s.buf[s.parity][0], s.buf[s.parity][1], s.n, b->ws, b->stream, out);
 }
 
+gs_status gs_batch_fill_cube(gs_batch *b, int32_t sim, int32_t x0, int32_t y0, int32_t z0, int32_t side, double cu,
+                             double cv)
+{
+    gs_status st = bcheck(b);
+    if (st != GS_OK) return st;
+    if ((st = sim_index(b, sim)) != GS_OK) return st;
+    const BSim &s = b->sims[sim];
+    const int mn = std::min(s.nx, std::min(s.ny, s.nz));
+    if (side < 1 || side > mn) return fail(GS_ERR_INVALID_ARG, "side %d outside [1, %d]", side, mn);
+    if (x0 < 0 || y0 < 0 || z0 < 0 || x0 >= s.nx || y0 >= s.ny || z0 >= s.nz)
+        return fail(GS_ERR_INVALID_ARG, "corner outside the grid");
+    if (!std::isfinite(cu) || !std::isfinite(cv)) return fail(GS_ERR_INVALID_ARG, "cube values must be finite");
+    hipError_t e = gs::launch_init_box(b->base.storage, s.buf[s.parity][0], s.buf[s.parity][1], s.nx, s.ny, s.nz, x0,
+                                       y0, z0, side, cu, cv, b->stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "fill kernel launch");
+}
+
 gs_status gs_batch_sync(gs_batch *b)
 {
     gs_status st = bcheck(b);

@@ -58,6 +58,14 @@ hipError_t launch_laplacian7(const double *f, double *out, int nx, int ny, int n
 hipError_t launch_init_cube(int storage, void *u, void *v, int nx, int ny, int nz, int side,
                             double cu, double cv, hipStream_t st);
 
+// Periodic cube at an arbitrary corner (u, v) = (cu, cv) in a (1, 0) background.
+hipError_t launch_init_box(int storage, void *u, void *v, int nx, int ny, int nz, int x0, int y0, int z0, int side,
+                           double cu, double cv, hipStream_t st);
+
+// Per-workgroup FP64 partial sums of (a - b)^2 (sqdiff_blocks() doubles).
+int sqdiff_blocks();
+hipError_t launch_sqdiff(int storage, const void *a, const void *b, size_t n, double *part, hipStream_t st);
+
 // Diagnostics: per-block partials into `ws`, then one block folds them.
 // Result (9 doubles: sum_u, comp_u, sum_v, comp_v, min_u, max_u, min_v,
 // max_v, nonfinite as double) lands at ws + diag_result_offset().

@@ -107,6 +107,11 @@ SIGNATURES = [
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("gs_surrogate_adam", _I32, [_SIM, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     ("gs_surrogate_destroy", _I32, [_SIM]),
+    ("gs_set_step", _I32, [_SIM, ctypes.c_uint64]),
+    ("gs_fill_cube", _I32, [_SIM, _I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double]),
+    ("gs_batch_fill_cube", _I32, [_SIM, _I32, _I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double]),
+    ("gs_sqdiff_workspace_bytes", _SZ, []),
+    ("gs_sqdiff", _I32, [_VP, _VP, _SZ, _I32, _VP, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("gs_laplacian7", _I32, [_VP, _VP, _I32, _I32, _I32, _VP]),
     ("gs_copy", _I32, [_VP, _VP, _SZ, _VP]),
 ]
@@ -256,6 +261,15 @@ class Sim:
         return dict(sum_u=d.sum_u, sum_v=d.sum_v, min_u=d.min_u, max_u=d.max_u, min_v=d.min_v,
                     max_v=d.max_v, nonfinite=int(d.nonfinite))
 
+    def advance_index(self, n: int):
+        """Advance the step index by n without computing steps (the state was
+        replaced by other means)."""
+        _, _, st = self.current()
+        check(load().gs_set_step(self.h, st + int(n)))
+
+    def fill_cube(self, x0, y0, z0, side, cu=0.25, cv=0.33):
+        check(load().gs_fill_cube(self.h, int(x0), int(y0), int(z0), int(side), float(cu), float(cv)))
+
     def sync(self):
         check(load().gs_sync(self.h))
 
@@ -355,6 +369,9 @@ class Batch:
         return dict(sum_u=d.sum_u, sum_v=d.sum_v, min_u=d.min_u, max_u=d.max_u, min_v=d.min_v,
                     max_v=d.max_v, nonfinite=int(d.nonfinite))
 
+    def fill_cube(self, sim, x0, y0, z0, side, cu=0.25, cv=0.33):
+        check(load().gs_batch_fill_cube(self.h, int(sim), int(x0), int(y0), int(z0), int(side), float(cu), float(cv)))
+
     def sync(self):
         check(load().gs_batch_sync(self.h))
 
@@ -368,6 +385,24 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+_sqdiff_ws = {}
+
+
+def sqdiff(a, b, stream=None):
+    """Sum of (a - b)^2 in FP64 over two equal CUDA tensors (library kernel)."""
+    import torch
+    assert a.is_cuda and b.is_cuda and a.dtype == b.dtype and a.numel() == b.numel()
+    assert a.is_contiguous() and b.is_contiguous()
+    storage = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}[a.dtype]
+    dev = a.device
+    if dev not in _sqdiff_ws:
+        _sqdiff_ws[dev] = torch.empty(int(load().gs_sqdiff_workspace_bytes()), dtype=torch.uint8, device=dev)
+    out = ctypes.c_double()
+    check(load().gs_sqdiff(a.data_ptr(), b.data_ptr(), a.numel(), storage, _sqdiff_ws[dev].data_ptr(),
+                           _stream_handle(stream), ctypes.byref(out)))
+    return out.value
 
 
 def laplacian7(f, out=None, stream=None):

@@ -87,3 +87,22 @@ def conv_weights(c_in: int, c_out: int, seed: int, scale: float | None = None):
     w = rng.normal(0.0, scale, size=(c_out, c_in, 3, 3, 3))
     b = rng.normal(0.0, 0.01, size=(c_out,))
     return w, b
+
+
+SURROGATE_CHANNELS = (4, 32, 32, 32, 2)
+
+
+def surrogate_init(seed: int):
+    """Initial parameters of the 16-step surrogate network as one flat float32
+    vector (per layer W[c_out][c_in][3][3][3] then b[c_out]): He-normal
+    weights, last layer scaled by 0.1 (the network starts near the identity
+    map through its residual output), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    ch = SURROGATE_CHANNELS
+    for l in range(4):
+        ci, co = ch[l], ch[l + 1]
+        scale = np.sqrt(2.0 / (ci * 27)) * (0.1 if l == 3 else 1.0)
+        parts.append(rng.normal(0.0, scale, size=co * ci * 27))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,150 @@
+"""The surrogate network on the GPU (MFMA BF16 kernels) against the FP64
+network oracle, its training, and the stencil-fallback controller.
+
+Tolerances: activations and weights are BF16 (8 significant bits, relative
+rounding 2^-9 per value) with FP32 accumulation; over four layers the
+relative error of the network's output correction is expected near 1e-2,
+so outputs are compared with relative L2 error <= 3e-2 and gradients with
+relative L2 error <= 6e-2 and cosine >= 0.998 per layer."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import surrogate_oracle as S
+from synth import random_blobs, surrogate_init
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def bf16_round(x):
+    x = np.asarray(x, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _params(seed, last_scale=3.0):
+    p = surrogate_init(seed).astype(np.float64)
+    # larger last layer and nonzero biases so the correction is not tiny
+    params = S.unflatten(p)
+    rng = np.random.default_rng(seed + 1)
+    params = [(W * (last_scale if l == 3 else 1.0), rng.normal(0, 0.05, size=b.shape)) for l, (W, b) in enumerate(params)]
+    return S.flatten(params).astype(np.float32)
+
+
+def _fields(shape, n, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.2, 1.0, size=(n,) + shape)
+    v = rng.uniform(0.0, 0.45, size=(n,) + shape)
+    return u, v
+
+
+def test_forward_matches_oracle(torch):
+    from paper_2309_10292_amd.surrogate import Surrogate
+    shape = (8, 12, 16)
+    n = 2
+    p32 = _params(3)
+    u, v = _fields(shape, n, 4)
+    F, k = np.array([0.02, 0.05]), np.array([0.048, 0.062])
+    with Surrogate(16, 12, 8, max_batch=n, params=p32) as m:
+        ut = torch.from_numpy(u).cuda()
+        vt = torch.from_numpy(v).cuda()
+        pu, pv = m.predict(ut, vt, F, k)
+        pu, pv = pu.cpu().numpy(), pv.cpu().numpy()
+        # FP32 input path gives the same correction
+        pu32, _ = m.predict(ut.float(), vt.float(), F, k)
+    params = S.unflatten(bf16_round(p32))
+    for i in range(n):
+        (eu, ev) = S.forward(params, bf16_round(u[i]), bf16_round(v[i]), float(np.float32(F[i])), float(np.float32(k[i])))
+        du_e, dv_e = eu - bf16_round(u[i]), ev - bf16_round(v[i])
+        du_g, dv_g = pu[i] - u[i], pv[i] - v[i]
+        ref = np.concatenate([du_e.ravel(), dv_e.ravel()])
+        got = np.concatenate([du_g.ravel(), dv_g.ravel()])
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"sample {i}: relative L2 of the correction {rel:.3e}, |ref| max {np.max(np.abs(ref)):.3e}")
+        assert rel <= 3e-2, rel
+    assert np.max(np.abs(pu32.cpu().numpy() - pu)) <= 1e-6 + 1e-2 * np.max(np.abs(pu - u))
+
+
+def test_gradients_match_oracle(torch):
+    from paper_2309_10292_amd.surrogate import Surrogate
+    shape = (4, 8, 16)
+    n = 2
+    p32 = _params(7, last_scale=1.0)
+    u, v = _fields(shape, n, 8)
+    rng = np.random.default_rng(9)
+    ut = u + 0.02 * rng.normal(size=u.shape)
+    vt = v + 0.02 * rng.normal(size=v.shape)
+    F, k = np.array([0.03, 0.045]), np.array([0.05, 0.06])
+    with Surrogate(16, 8, 4, max_batch=n, params=p32) as m:
+        T = lambda a: torch.from_numpy(a.astype(np.float32)).cuda().contiguous()
+        loss, g = m.loss_grad(T(u), T(v), T(ut), T(vt), F, k, want_grad=True)
+    params = S.unflatten(bf16_round(p32))
+    # The network sees BF16-rounded (u, v) while the residual adds the FP32
+    # fields; shifting the oracle's targets by the rounding difference makes
+    # its residuals equal to the GPU's.
+    samples = []
+    for i in range(n):
+        u32, v32 = u[i].astype(np.float32).astype(np.float64), v[i].astype(np.float32).astype(np.float64)
+        ub, vb = bf16_round(u[i]), bf16_round(v[i])
+        samples.append((ub, vb, float(np.float32(F[i])), float(np.float32(k[i])),
+                        ut[i].astype(np.float32).astype(np.float64) - (u32 - ub),
+                        vt[i].astype(np.float32).astype(np.float64) - (v32 - vb)))
+    loss_e, grads = S.loss_and_grads(params, samples)
+    print(f"loss gpu {loss:.6e} oracle {loss_e:.6e}")
+    assert abs(loss - loss_e) <= 3e-2 * loss_e
+    ge = S.flatten(grads)
+    o = 0
+    for l, (W, b) in enumerate(grads):
+        for arr in (W, b):
+            a = g[o:o + arr.size].astype(np.float64)
+            e = arr.ravel()
+            o += arr.size
+            rel = np.linalg.norm(a - e) / np.linalg.norm(e)
+            cos = float(a @ e / (np.linalg.norm(a) * np.linalg.norm(e)))
+            print(f"layer {l} {'W' if arr is W else 'b'}: rel {rel:.3e} cos {cos:.6f}")
+            assert rel <= 6e-2 and cos >= 0.998, (l, rel, cos)
+    assert o == ge.size
+
+
+def test_training_reduces_loss_and_controller(torch):
+    """Stencil-generated pairs (batched sweeps, random blobs) at L=32; a few
+    hundred Adam steps must cut the loss; the controller keeps the stencil
+    result whenever the check fails and matches the plain stencil when every
+    jump is checked and rejected."""
+    from paper_2309_10292_amd import gs
+    from paper_2309_10292_amd.surrogate import Surrogate, generate_pairs, run_controlled, train
+    L = 32
+    blobs = random_blobs(8, L, seed=12, side_range=(4, 10))
+    data = generate_pairs(L, blobs, steps_total=160, pair_every=32, warm=16)
+    # pairs start at 16, 48, 80, 112, 144 (the last ends at step 160)
+    assert data[0].shape[0] == 8 * 5
+    with Surrogate(L, L, L, max_batch=4, params=surrogate_init(1)) as m:
+        l0, _ = m.loss_grad(data[0][:4].contiguous(), data[1][:4].contiguous(), data[2][:4].contiguous(),
+                            data[3][:4].contiguous(), data[4][:4], data[5][:4])
+        hist = train(m, data, iters=150, batch=4, lr=2e-3, seed=0)
+        print(f"loss {l0:.3e} -> {np.mean(hist[-10:]):.3e}")
+        assert np.mean(hist[-10:]) < 0.5 * l0
+        # controller: every jump checked with tol 0 -> always the stencil
+        b = blobs[0]
+        with gs.Sim(L, L, L, init="none", u0=np.ones((L, L, L)), v0=np.zeros((L, L, L)), F=b["F"], k=b["k"]) as s:
+            s.fill_cube(b["x0"], b["y0"], b["z0"], b["side"])
+            u0, v0 = s.read()
+            r = run_controlled(m, s, b["F"], b["k"], jumps=3, check_every=1, tol=0.0)
+            assert r["checks"] == 3 and r["fallbacks"] == 3
+            u, v = s.read()
+            assert s.current()[2] == 48
+        ue, ve = O.run(u0, v0, 48, Du=0.2, Dv=0.1, F=b["F"], k=b["k"], dt=1.0)
+        assert np.array_equal(u, ue) and np.array_equal(v, ve)
+        # with an infinite tolerance no check falls back
+        with gs.Sim(L, L, L, init="none", u0=u0, v0=v0, F=b["F"], k=b["k"]) as s:
+            r = run_controlled(m, s, b["F"], b["k"], jumps=8, check_every=4, tol=float("inf"))
+            assert r["checks"] == 2 and r["fallbacks"] == 0 and len(r["rms"]) == 2
+            assert s.current()[2] == 128
+            print(f"controller rms at checks: {r['rms']}")
