@@ -86,33 +86,51 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const bf16x8 bv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+                // A = weights (rows: output channels), B = activations (columns:
+                // cells), so a lane's accumulators are 4 consecutive output
+                // channels of one cell.
+                const bf16x8 wv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
             }
         }
-        // acc[t][j]: cell c0 + 4 quad + j, output channel 16 t + col.
+        // acc[t][j]: output channel 16 t + 4 quad + j of cell row0 + col.
+        const size_t r = row0 + col;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int co = 16 * t + col;
+            const int co0 = 16 * t + 4 * quad;
+            if constexpr (MODE == MODE_HIDDEN) {
+                uint2 zq, aq;
+                u16 zb[4], ab[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const size_t r = row0 + 4 * quad + j;
-                const float v = acc[t][j];
-                if constexpr (MODE == MODE_HIDDEN) {
-                    const float zz = v + a.bias[co];
-                    a.zout[r * 32 + co] = f2bf(zz);
-                    a.aout[r * 32 + co] = f2bf(gelu(zz));
-                } else if constexpr (MODE == MODE_OUT) {
-                    if (co < 2) {
-                        // r = s * ncell + cell indexes the planar (sample, cell) fields
-                        const IO *res = co == 0 ? (const IO *)a.res_u : (const IO *)a.res_v;
-                        IO *out = co == 0 ? (IO *)a.out_u : (IO *)a.out_v;
-                        out[r] = res[r] + (IO)(v + a.bias[co]);
-                    }
-                } else {
-                    const float zp = bf2f(a.zprev[r * 32 + co]);
-                    a.aout[r * 32 + co] = f2bf(v * gelu_grad(zp));
+                for (int j = 0; j < 4; ++j) {
+                    const float zz = acc[t][j] + a.bias[co0 + j];
+                    zb[j] = f2bf(zz);
+                    ab[j] = f2bf(gelu(zz));
                 }
+                zq.x = (uint32_t)zb[0] | ((uint32_t)zb[1] << 16);
+                zq.y = (uint32_t)zb[2] | ((uint32_t)zb[3] << 16);
+                aq.x = (uint32_t)ab[0] | ((uint32_t)ab[1] << 16);
+                aq.y = (uint32_t)ab[2] | ((uint32_t)ab[3] << 16);
+                *reinterpret_cast<uint2 *>(a.zout + r * 32 + co0) = zq;
+                *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = aq;
+            } else if constexpr (MODE == MODE_OUT) {
+                if (quad == 0) {
+                    // r = s * ncell + cell indexes the planar (sample, cell) fields
+                    const IO *ru = (const IO *)a.res_u, *rv = (const IO *)a.res_v;
+                    ((IO *)a.out_u)[r] = ru[r] + (IO)(acc[t][0] + a.bias[0]);
+                    ((IO *)a.out_v)[r] = rv[r] + (IO)(acc[t][1] + a.bias[1]);
+                }
+            } else {
+                const uint2 zq = *reinterpret_cast<const uint2 *>(a.zprev + r * 32 + co0);
+                const float zp[4] = {bf2f((u16)(zq.x & 0xffffu)), bf2f((u16)(zq.x >> 16)), bf2f((u16)(zq.y & 0xffffu)),
+                                     bf2f((u16)(zq.y >> 16))};
+                u16 gb[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) gb[j] = f2bf(acc[t][j] * gelu_grad(zp[j]));
+                uint2 gq;
+                gq.x = (uint32_t)gb[0] | ((uint32_t)gb[1] << 16);
+                gq.y = (uint32_t)gb[2] | ((uint32_t)gb[3] << 16);
+                *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = gq;
             }
         }
     }

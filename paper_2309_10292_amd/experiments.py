@@ -93,14 +93,26 @@ def batched(args):
         out["batch_tuned_graph"] = dict(ms=round(ms, 2), gcells=round(cells * n / (ms * 1e-3) / 1e9, 2))
         ms = _timed(torch, lambda: b.step(n))
         out["batch_tuned"] = dict(ms=round(ms, 2), gcells=round(cells * n / (ms * 1e-3) / 1e9, 2))
-    # the same simulations, each alone with the library's default single-grid path
-    total = 0.0
-    for s in sims:
-        with gs.Sim(s["L"], s["L"], s["L"], F=s["F"], k=s["k"], **base) as one:
-            one.step(2)
-            total += _timed(torch, lambda: one.step(n))
-    out["each_alone"] = dict(ms=round(total, 2), gcells=round(cells * n / (total * 1e-3) / 1e9, 2))
-    out["speedup_batched_vs_alone"] = round(total / out["batch_tuned_graph"]["ms"], 2)
+    # the same simulations, each alone with the single-grid path: with the
+    # library defaults, and with the configuration gs_tune picks for that size
+    tuned = {}
+    for L in sorted({s["L"] for s in sims}):
+        with gs.Sim(L, L, L, F=0.03, k=0.055, **base) as one:
+            cfg, _ = one.tune(reps=2)
+            tuned[L] = cfg
+    out["alone_tuned_configs"] = {str(L): c for L, c in tuned.items()}
+    for label, use_tuned in (("each_alone_default", False), ("each_alone_tuned", True)):
+        total = 0.0
+        for s in sims:
+            with gs.Sim(s["L"], s["L"], s["L"], F=s["F"], k=s["k"], **base) as one:
+                if use_tuned:
+                    c = tuned[s["L"]]
+                    one.set_config(c["tile"], c["tblock"], c["zchunk"])
+                one.step(2)
+                total += _timed(torch, lambda: one.step_graph(n) if use_tuned else one.step(n))
+        out[label] = dict(ms=round(total, 2), gcells=round(cells * n / (total * 1e-3) / 1e9, 2))
+    out["speedup_batched_vs_alone_tuned"] = round(out["each_alone_tuned"]["ms"] / out["batch_tuned_graph"]["ms"], 2)
+    out["speedup_batched_vs_alone_default"] = round(out["each_alone_default"]["ms"] / out["batch_tuned_graph"]["ms"], 2)
     return out
 
 
@@ -118,7 +130,7 @@ def surrogate(args):
                batch=args.batch, lr=args.lr)
     blobs = random_blobs(args.trajectories + args.held_out, L, seed=230910292, side_range=(6, 24))
     train_blobs, test_blobs = blobs[:args.trajectories], blobs[args.trajectories:]
-    hist = []
+    hist, curve = [], []
     t_gen = t_train = 0.0
     with Surrogate(L, L, L, max_batch=args.batch, params=surrogate_init(0)) as m:
         for c0 in range(0, len(train_blobs), args.chunk):
@@ -134,10 +146,11 @@ def surrogate(args):
             t_gen += t1 - t0
             t_train += time.perf_counter() - t1
             del data
+            curve.append((len(hist), float(np.mean(hist[-20:]))))
             print(json.dumps(dict(chunk=c0 // args.chunk, iters=len(hist), loss=float(np.mean(hist[-20:])),
                                   gen_s=round(t_gen, 1), train_s=round(t_train, 1))), flush=True)
         out["train"] = dict(iters=len(hist), loss_first=float(np.mean(hist[:20])), loss_last=float(np.mean(hist[-50:])),
-                            generate_seconds=round(t_gen, 1), train_seconds=round(t_train, 1))
+                            generate_seconds=round(t_gen, 1), train_seconds=round(t_train, 1), curve=curve)
         params = m.params()
         if args.save:
             np.save(args.save, params)
@@ -146,6 +159,7 @@ def surrogate(args):
         with gs.Sim(L, L, L, init="none", u0=np.ones((L,) * 3), v0=np.zeros((L,) * 3), F=b["F"], k=b["k"]) as s:
             s.fill_cube(b["x0"], b["y0"], b["z0"], b["side"])
             s.step(args.warm)
+            s.tune(reps=2)  # the stencil side gets its autotuned configuration
             u, v, _ = s.current()
             pu, pv = torch.empty_like(u), torch.empty_like(v)
             m.predict(u, v, b["F"], b["k"], pu, pv)

@@ -261,6 +261,10 @@ class Sim:
         return dict(sum_u=d.sum_u, sum_v=d.sum_v, min_u=d.min_u, max_u=d.max_u, min_v=d.min_v,
                     max_v=d.max_v, nonfinite=int(d.nonfinite))
 
+    def set_index(self, step: int):
+        """Set the global step index of the current state (gs_set_step)."""
+        check(load().gs_set_step(self.h, int(step)))
+
     def advance_index(self, n: int):
         """Advance the step index by n without computing steps (the state was
         replaced by other means)."""

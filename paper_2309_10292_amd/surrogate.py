@@ -9,6 +9,7 @@ error checks all run in libgs's kernels.
 from __future__ import annotations
 
 import ctypes
+import math
 import time
 
 import numpy as np
@@ -163,36 +164,50 @@ def train(model: Surrogate, data, iters, batch, lr=1e-3, seed=0, log_every=0, lr
 
 
 def run_controlled(model: Surrogate, sim, F, k, jumps, check_every=4, tol=1e-3):
-    """Advances `sim` (a gs.Sim, FP64) by jumps x JUMP steps with surrogate
-    jumps; every `check_every`-th jump is also computed with the stencil, and
-    when the RMS difference over both fields exceeds `tol` the stencil result
-    is kept (a fallback). Returns a dict of counts, errors and timings."""
+    """Advances `sim` (a gs.Sim) by jumps x JUMP steps with surrogate jumps in
+    windows of `check_every` jumps. The last jump of every window is also
+    computed with the stencil from the same state; if the RMS difference over
+    both fields exceeds `tol` (or is not finite), the whole window is rolled
+    back to its verified starting state and recomputed with the stencil (a
+    fallback). Returns counts, the RMS of every check and the wall time."""
     import torch
     st = torch.cuda.current_stream()
     fallbacks, checks, errors = 0, 0, []
     u, v, _ = sim.current()
     pu, pv = torch.empty_like(u), torch.empty_like(v)
+    snap_u, snap_v = torch.empty_like(u), torch.empty_like(v)
     t0 = time.perf_counter()
-    for j in range(jumps):
-        u, v, _ = sim.current()
-        model.predict(u, v, F, k, pu, pv)
-        if (j + 1) % check_every == 0:
+    j = 0
+    while j < jumps:
+        w = min(check_every, jumps - j)
+        u, v, step0 = sim.current()
+        gs.copy(u, snap_u)
+        gs.copy(v, snap_v)
+        for i in range(w):
+            u, v, _ = sim.current()
+            model.predict(u, v, F, k, pu, pv)
+            if i < w - 1 or w < check_every:
+                # unchecked jump: the prediction becomes the state
+                gs.copy(pu, u)
+                gs.copy(pv, v)
+                sim.advance_index(JUMP)
+                continue
             checks += 1
             sim.step(JUMP)
             su, sv, _ = sim.current()
             rms = ((gs.sqdiff(pu, su) + gs.sqdiff(pv, sv)) / (2 * su.numel())) ** 0.5
             errors.append(rms)
-            if rms > tol:
+            if math.isfinite(rms) and rms <= tol:
+                gs.copy(pu, su)
+                gs.copy(pv, sv)
+            else:
                 fallbacks += 1
-                continue  # keep the stencil state
-            gs.copy(pu, su)
-            gs.copy(pv, sv)
-        else:
-            # accept: write the prediction into the simulation's current state
-            # and advance its step index without computing steps
-            gs.copy(pu, u)
-            gs.copy(pv, v)
-            sim.advance_index(JUMP)
+                u, v, _ = sim.current()
+                gs.copy(snap_u, u)
+                gs.copy(snap_v, v)
+                sim.set_index(step0)
+                sim.step(w * JUMP)
+        j += w
     st.synchronize()
     el = time.perf_counter() - t0
     return dict(jumps=jumps, checks=checks, fallbacks=fallbacks, rms=errors, seconds=el)

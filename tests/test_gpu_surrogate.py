@@ -142,9 +142,29 @@ def test_training_reduces_loss_and_controller(torch):
             assert s.current()[2] == 48
         ue, ve = O.run(u0, v0, 48, Du=0.2, Dv=0.1, F=b["F"], k=b["k"], dt=1.0)
         assert np.array_equal(u, ue) and np.array_equal(v, ve)
+        # a failed check rolls the whole window back to its verified start and
+        # recomputes it with the stencil: tol 0 with windows of 4 jumps gives
+        # the plain stencil result too
+        with gs.Sim(L, L, L, init="none", u0=u0, v0=v0, F=b["F"], k=b["k"]) as s:
+            r = run_controlled(m, s, b["F"], b["k"], jumps=8, check_every=4, tol=0.0)
+            assert r["checks"] == 2 and r["fallbacks"] == 2
+            assert s.current()[2] == 128
+            u, v = s.read()
+        ue, ve = O.run(u0, v0, 128, Du=0.2, Dv=0.1, F=b["F"], k=b["k"], dt=1.0)
+        assert np.array_equal(u, ue) and np.array_equal(v, ve)
         # with an infinite tolerance no check falls back
         with gs.Sim(L, L, L, init="none", u0=u0, v0=v0, F=b["F"], k=b["k"]) as s:
             r = run_controlled(m, s, b["F"], b["k"], jumps=8, check_every=4, tol=float("inf"))
             assert r["checks"] == 2 and r["fallbacks"] == 0 and len(r["rms"]) == 2
             assert s.current()[2] == 128
             print(f"controller rms at checks: {r['rms']}")
+        # a network that produces non-finite values is always caught
+        bad = m.params()
+        bad[-200:] = np.float32(3e38)
+        m.set_params(bad)
+        with gs.Sim(L, L, L, init="none", u0=u0, v0=v0, F=b["F"], k=b["k"]) as s:
+            r = run_controlled(m, s, b["F"], b["k"], jumps=4, check_every=4, tol=1.0)
+            assert r["fallbacks"] == 1
+            u, v = s.read()
+        ue, ve = O.run(u0, v0, 64, Du=0.2, Dv=0.1, F=b["F"], k=b["k"], dt=1.0)
+        assert np.array_equal(u, ue) and np.array_equal(v, ve)
