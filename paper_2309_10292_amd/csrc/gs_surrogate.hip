@@ -51,26 +51,70 @@ __device__ __forceinline__ size_t nbr_row(const Geo &g, int s, int x, int y, int
 // MODE_OUT:    pred = residual input + acc + bias for output channels 0, 1.
 // MODE_DGRAD:  writes acc * GELU'(zprev) (the gradient of the layer below's
 //              pre-activation, 32 channels, BF16).
+//
+// A workgroup (4 wavefronts) owns a patch of 16 x-cells by 4 y-rows of one
+// sample and marches through a chunk of z planes; wavefront w computes row w
+// (one 16-cell M tile per plane). The input planes z-1, z, z+1 of the patch
+// with a one-cell ring (18 x 6 cells) sit in an LDS ring of three planes next
+// to the packed weights, so every input value is fetched from L2 once per
+// chunk instead of once per offset; the plane z+2 is loaded into registers
+// while plane z is computed.
+constexpr int PX = 16, PY = 4;               // patch (x, y)
+constexpr int RX = PX + 2, RY = PY + 2;      // ring plane (x, y)
+constexpr int RCELLS = RX * RY;              // cells per ring plane
+
 template <int CIN, int NT, int MODE, typename IO>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
 {
     constexpr int NCH = (27 * CIN + 31) / 32;
+    constexpr int VPC = CIN / 8;              // 16-byte vectors per cell
+    constexpr int PLANE_V = RCELLS * VPC;     // 16-byte vectors per ring plane
+    constexpr int LOADS = (PLANE_V + 255) / 256;
     __shared__ uint4 wl[NCH * NT * 64];
+    __shared__ uint4 ring[3 * PLANE_V];
     const uint4 *wg = reinterpret_cast<const uint4 *>(a.wpack);
     for (int i = threadIdx.x; i < NCH * NT * 64; i += 256) wl[i] = wg[i];
-    __syncthreads();
 
     const Geo g = a.geo;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, quad = lane >> 4;
-    const size_t rows = (size_t)a.nsamp * g.ncell;
-    const size_t n_mt = rows / 16;
-    for (size_t mt = (size_t)blockIdx.x * 4 + wave; mt < n_mt; mt += (size_t)gridDim.x * 4) {
-        const size_t row0 = mt * 16;
-        const int s = (int)(row0 / g.ncell);
-        const int c0 = (int)(row0 % g.ncell);
-        const int x0 = c0 % g.nx, y = (c0 / g.nx) % g.ny, z = c0 / (g.nx * g.ny);
+    const int tx = g.nx / PX, ty = (g.ny + PY - 1) / PY, tzc = (g.nz + a.zc - 1) / a.zc;
+    int b = blockIdx.x;
+    const int bx = b % tx;
+    b /= tx;
+    const int by = b % ty;
+    b /= ty;
+    const int bz = b % tzc;
+    const int s = b / tzc;
+    const int x0 = bx * PX, y0 = by * PY, z0 = bz * a.zc;
+    const int ze = min(z0 + a.zc, g.nz);
+    const size_t sbase = (size_t)s * g.ncell;
+
+    // global address of ring vector v (cell (rx, ry) of plane z, channel group cg)
+    auto ring_src = [&](int v, int z) -> const uint4 * {
+        const int cell = v / VPC, cg = v % VPC;
+        const int rx = cell % RX, ry = cell / RX;
+        const int gx = wrapc(x0 + rx - 1, g.nx), gy = wrapc(y0 + ry - 1, g.ny), gz = wrapc(z, g.nz);
+        const size_t row = sbase + (size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz);
+        return reinterpret_cast<const uint4 *>(a.in + row * CIN) + cg;
+    };
+    for (int p = 0; p < 3; ++p) {
+        const int z = z0 - 1 + p; // ring slot of plane z is (z mod 3)
+        const int slot = ((z % 3) + 3) % 3;
+        for (int v = threadIdx.x; v < PLANE_V; v += 256) ring[slot * PLANE_V + v] = *ring_src(v, z);
+    }
+    __syncthreads();
+
+    const int yrow = y0 + wave;
+    const bool row_ok = yrow < g.ny;
+    for (int z = z0; z < ze; ++z) {
+        // prefetch plane z+2 (needed from the next plane on); every lane loads
+        // an in-range vector (indices clamped) and only the LDS store is masked
+        const bool more = z + 1 < ze;
+        static_assert(LOADS <= 2, "a ring plane is at most two vectors per lane");
+        const uint4 pre0 = *ring_src(min((int)threadIdx.x, PLANE_V - 1), z + 2);
+        const uint4 pre1 = LOADS > 1 ? *ring_src(min((int)threadIdx.x + 256, PLANE_V - 1), z + 2) : pre0;
         f32x4 acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -80,7 +124,10 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
             const int d = k0 / CIN, ci0 = k0 % CIN;
             bf16x8 av;
             if (d < 27) {
-                av = load8(a.in + nbr_row(g, s, x0 + col, y, z, d) * CIN + ci0);
+                const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
+                const int slot = (((z + dz - 1) % 3) + 3) % 3;
+                const int cell = (wave + dy) * RX + col + dx;
+                av = __builtin_bit_cast(bf16x8, ring[slot * PLANE_V + cell * VPC + ci0 / 8]);
             } else {
                 av = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
             }
@@ -93,46 +140,55 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
             }
         }
-        // acc[t][j]: output channel 16 t + 4 quad + j of cell row0 + col.
-        const size_t r = row0 + col;
+        // acc[t][j]: output channel 16 t + 4 quad + j of cell (x0 + col, yrow, z).
+        const size_t r = sbase + (size_t)(x0 + col) + (size_t)g.nx * ((size_t)yrow + (size_t)g.ny * z);
+        if (row_ok) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int co0 = 16 * t + 4 * quad;
-            if constexpr (MODE == MODE_HIDDEN) {
-                uint2 zq, aq;
-                u16 zb[4], ab[4];
+            for (int t = 0; t < NT; ++t) {
+                const int co0 = 16 * t + 4 * quad;
+                if constexpr (MODE == MODE_HIDDEN) {
+                    uint2 zq, aq;
+                    u16 zb[4], ab[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float zz = acc[t][j] + a.bias[co0 + j];
-                    zb[j] = f2bf(zz);
-                    ab[j] = f2bf(gelu(zz));
+                    for (int j = 0; j < 4; ++j) {
+                        const float zz = acc[t][j] + a.bias[co0 + j];
+                        zb[j] = f2bf(zz);
+                        ab[j] = f2bf(gelu(zz));
+                    }
+                    zq.x = (uint32_t)zb[0] | ((uint32_t)zb[1] << 16);
+                    zq.y = (uint32_t)zb[2] | ((uint32_t)zb[3] << 16);
+                    aq.x = (uint32_t)ab[0] | ((uint32_t)ab[1] << 16);
+                    aq.y = (uint32_t)ab[2] | ((uint32_t)ab[3] << 16);
+                    *reinterpret_cast<uint2 *>(a.zout + r * 32 + co0) = zq;
+                    *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = aq;
+                } else if constexpr (MODE == MODE_OUT) {
+                    if (quad == 0) {
+                        // r = s * ncell + cell indexes the planar (sample, cell) fields
+                        const IO *ru = (const IO *)a.res_u, *rv = (const IO *)a.res_v;
+                        ((IO *)a.out_u)[r] = ru[r] + (IO)(acc[t][0] + a.bias[0]);
+                        ((IO *)a.out_v)[r] = rv[r] + (IO)(acc[t][1] + a.bias[1]);
+                    }
+                } else {
+                    const uint2 zq = *reinterpret_cast<const uint2 *>(a.zprev + r * 32 + co0);
+                    const float zp[4] = {bf2f((u16)(zq.x & 0xffffu)), bf2f((u16)(zq.x >> 16)),
+                                         bf2f((u16)(zq.y & 0xffffu)), bf2f((u16)(zq.y >> 16))};
+                    u16 gb[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) gb[j] = f2bf(acc[t][j] * gelu_grad(zp[j]));
+                    uint2 gq;
+                    gq.x = (uint32_t)gb[0] | ((uint32_t)gb[1] << 16);
+                    gq.y = (uint32_t)gb[2] | ((uint32_t)gb[3] << 16);
+                    *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = gq;
                 }
-                zq.x = (uint32_t)zb[0] | ((uint32_t)zb[1] << 16);
-                zq.y = (uint32_t)zb[2] | ((uint32_t)zb[3] << 16);
-                aq.x = (uint32_t)ab[0] | ((uint32_t)ab[1] << 16);
-                aq.y = (uint32_t)ab[2] | ((uint32_t)ab[3] << 16);
-                *reinterpret_cast<uint2 *>(a.zout + r * 32 + co0) = zq;
-                *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = aq;
-            } else if constexpr (MODE == MODE_OUT) {
-                if (quad == 0) {
-                    // r = s * ncell + cell indexes the planar (sample, cell) fields
-                    const IO *ru = (const IO *)a.res_u, *rv = (const IO *)a.res_v;
-                    ((IO *)a.out_u)[r] = ru[r] + (IO)(acc[t][0] + a.bias[0]);
-                    ((IO *)a.out_v)[r] = rv[r] + (IO)(acc[t][1] + a.bias[1]);
-                }
-            } else {
-                const uint2 zq = *reinterpret_cast<const uint2 *>(a.zprev + r * 32 + co0);
-                const float zp[4] = {bf2f((u16)(zq.x & 0xffffu)), bf2f((u16)(zq.x >> 16)), bf2f((u16)(zq.y & 0xffffu)),
-                                     bf2f((u16)(zq.y >> 16))};
-                u16 gb[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) gb[j] = f2bf(acc[t][j] * gelu_grad(zp[j]));
-                uint2 gq;
-                gq.x = (uint32_t)gb[0] | ((uint32_t)gb[1] << 16);
-                gq.y = (uint32_t)gb[2] | ((uint32_t)gb[3] << 16);
-                *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = gq;
             }
         }
+        __syncthreads(); // every read of plane z-1's slot is done
+        if (more) {
+            const int slot = ((z + 2) % 3 + 3) % 3;
+            if ((int)threadIdx.x < PLANE_V) ring[slot * PLANE_V + threadIdx.x] = pre0;
+            if (LOADS > 1 && (int)threadIdx.x + 256 < PLANE_V) ring[slot * PLANE_V + threadIdx.x + 256] = pre1;
+        }
+        __syncthreads();
     }
 }
 
@@ -156,6 +212,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[i][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) bsum[m] = 0.f;
     const size_t rows = (size_t)a.nsamp * g.ncell;
     const size_t n_kc = rows / 32;
     for (size_t kc = blockIdx.x; kc < n_kc; kc += gridDim.x) {
@@ -171,6 +230,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
             for (int j = 0; j < 8; ++j) {
                 const u16 b = co < COUTS ? a.dz[(r0 + j) * COUTS + co] : (u16)0;
                 av[m][j] = __builtin_bit_cast(__bf16, b);
+                bsum[m] += bf2f(b); // bias gradient: the same sum over cells without the input
             }
         }
 #pragma unroll
@@ -191,6 +251,16 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
                     acc[i][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[i][m][n], 0, 0, 0);
             }
         }
+    }
+    // Bias partials: lanes col, col + 16, col + 32, col + 48 hold the four
+    // 8-cell groups of channel 16 m + col; every wave loaded the same dz, so
+    // wave 0 writes them.
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        float t = bsum[m];
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        if (wave == 0 && quad == 0) a.bpart[(size_t)blockIdx.x * 32 + 16 * m + col] = t;
     }
     // acc[i][m][n][j]: offset d, co = 16 m + 4 quad + j, ci = 16 n + col.
     constexpr int PCO = 16 * MT, PCI = 16 * NT;
@@ -222,24 +292,7 @@ __global__ __launch_bounds__(256) void wgrad_reduce(const float *__restrict__ pa
     }
 }
 
-// Bias gradient: per-workgroup channel sums of dz, then a fixed-order fold.
-__global__ __launch_bounds__(256) void colsum_partial(const u16 *__restrict__ dz, size_t rows, int cs, int cout,
-                                                      float *__restrict__ part)
-{
-    __shared__ float red[256];
-    const int c = threadIdx.x % 32, r = threadIdx.x / 32; // 8 row lanes x 32 channels
-    float acc = 0.f;
-    if (c < cout)
-        for (size_t row = (size_t)blockIdx.x * 8 + r; row < rows; row += (size_t)gridDim.x * 8) acc += bf2f(dz[row * cs + c]);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (r == 0 && c < cout) {
-        float t = 0.f;
-        for (int i = 0; i < 8; ++i) t += red[i * 32 + c];
-        part[(size_t)blockIdx.x * 32 + c] = t;
-    }
-}
-
+// Bias gradient: fixed-order fold of the per-workgroup channel sums.
 __global__ __launch_bounds__(64) void colsum_reduce(const float *__restrict__ part, int nblk, int cout,
                                                     float *__restrict__ gb)
 {
@@ -344,8 +397,10 @@ static int grid_cap(size_t work, int per_block, int cap)
 
 hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a, hipStream_t st)
 {
-    const size_t mts = (size_t)a.nsamp * a.geo.ncell / 16;
-    const int grid = grid_cap(mts, 4, 256 * 16);
+    if (a.zc < 1 || a.geo.nx % PX != 0) return hipErrorInvalidValue;
+    const size_t blocks = (size_t)(a.geo.nx / PX) * ((a.geo.ny + PY - 1) / PY) * ((a.geo.nz + a.zc - 1) / a.zc) * a.nsamp;
+    if (blocks == 0 || blocks > 0x7fffffffu) return hipErrorInvalidConfiguration;
+    const int grid = (int)blocks;
 #define GS_CONV(CI, N, M, IO) hipLaunchKernelGGL((conv_kernel<CI, N, M, IO>), dim3(grid), dim3(256), 0, st, a)
     if (cin == 8 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(8, 2, MODE_HIDDEN, float);
     else if (cin == 32 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(32, 2, MODE_HIDDEN, float);
@@ -358,7 +413,7 @@ hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a,
     return hipGetLastError();
 }
 
-int wgrad_blocks() { return 256; }
+int wgrad_blocks() { return 512; }
 
 hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st)
 {
@@ -382,14 +437,9 @@ hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, in
     return hipGetLastError();
 }
 
-int colsum_blocks() { return 512; }
-
-hipError_t launch_bias_grad(const uint16_t *dz, size_t rows, int cs, int cout, float *part, float *gb, hipStream_t st)
+hipError_t launch_bias_reduce(const float *bpart, int cout, float *gb, hipStream_t st)
 {
-    hipLaunchKernelGGL(colsum_partial, dim3(colsum_blocks()), dim3(256), 0, st, dz, rows, cs, cout, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_reduce, dim3(1), dim3(64), 0, st, (const float *)part, colsum_blocks(), cout, gb);
+    hipLaunchKernelGGL(colsum_reduce, dim3(1), dim3(64), 0, st, bpart, wgrad_blocks(), cout, gb);
     return hipGetLastError();
 }
 

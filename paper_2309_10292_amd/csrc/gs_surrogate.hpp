@@ -22,6 +22,7 @@ struct Geo {
 struct ConvArgs {
     Geo geo;
     int nsamp;
+    int zc;                 // planes per workgroup chunk
     const uint16_t *in;     // channels-last BF16 input (CIN channels)
     const uint16_t *wpack;  // packed BF16 weights (B fragments)
     const float *bias;      // MODE_HIDDEN / MODE_OUT
@@ -38,14 +39,14 @@ struct WgradArgs {
     const uint16_t *dz;  // output gradient, COUTS channels
     const uint16_t *act; // layer input, CIN channels
     float *part;         // wgrad_blocks() x 27 x (16 MT) x (16 NT) partial sums
+    float *bpart;        // wgrad_blocks() x 32 partial sums of dz (bias gradient)
 };
 
 hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a, hipStream_t st);
 int wgrad_blocks();
 hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st);
 hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, float *gW, hipStream_t st);
-int colsum_blocks();
-hipError_t launch_bias_grad(const uint16_t *dz, size_t rows, int cs, int cout, float *part, float *gb, hipStream_t st);
+hipError_t launch_bias_reduce(const float *bpart, int cout, float *gb, hipStream_t st);
 hipError_t launch_pack_input(int io_f64, const void *u, const void *v, const float *fk, int nsamp, int ncell,
                              uint16_t *x, hipStream_t st);
 int loss_blocks();

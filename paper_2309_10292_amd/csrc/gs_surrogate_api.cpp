@@ -58,7 +58,7 @@ Layout layout(size_t cells, int B)
     for (int l = 1; l < 4; ++l) L.wd[l] = take((size_t)nchunks(l == 3 ? 8 : 32) * 2 * 512 * 2);
     L.wd[0] = 0;
     L.wpart = take((size_t)gs::nn::wgrad_blocks() * 27 * 32 * 32 * 4);
-    L.cpart = take((size_t)gs::nn::colsum_blocks() * 32 * 4);
+    L.cpart = take((size_t)gs::nn::wgrad_blocks() * 32 * 4);
     L.lpart = take((size_t)gs::nn::loss_blocks() * 8);
     L.fk = take((size_t)B * 2 * 4);
     L.total = o;
@@ -135,6 +135,16 @@ gs_status upload_fk(gs_surrogate *s, int32_t nsamp, const double *F, const doubl
     return e == hipSuccess ? GS_OK : hip_fail(e, "F/k upload");
 }
 
+// Planes per workgroup chunk of the convolutions: long chunks amortise the
+// two extra ring planes; shorter ones keep enough workgroups on small grids.
+int conv_zc(const gs_surrogate *s)
+{
+    const int patches = (s->geo.nx / 16) * ((s->geo.ny + 3) / 4);
+    int zc = 32;
+    while (zc > 4 && (size_t)patches * ((s->geo.nz + zc - 1) / zc) < 2048) zc /= 2;
+    return zc < s->geo.nz ? zc : s->geo.nz;
+}
+
 // Forward pass of nsamp samples; keeps pre-activations and activations.
 hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, const void *v, void *uo, void *vo)
 {
@@ -147,6 +157,7 @@ hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, co
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
+        a.zc = conv_zc(s);
         a.in = in;
         a.wpack = at<uint16_t>(s, s->L.wf[l]);
         a.bias = P + b_off(l);
@@ -159,6 +170,7 @@ hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, co
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
+        a.zc = conv_zc(s);
         a.in = in;
         a.wpack = at<uint16_t>(s, s->L.wf[3]);
         a.bias = P + b_off(3);
@@ -289,15 +301,17 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
         w.dz = dz;
         w.act = act_in[l];
         w.part = wpart;
+        w.bpart = cpart;
         e = launch_wgrad(k_cins[l], couts, w, s->stream);
         if (e == hipSuccess)
             e = launch_wgrad_reduce(wpart, couts == 8 ? 16 : 32, k_cins[l] == 8 ? 16 : 32, k_chan[l + 1], k_chan[l],
                                     G + w_off(l), s->stream);
-        if (e == hipSuccess) e = launch_bias_grad(dz, rows, couts, k_chan[l + 1], cpart, G + b_off(l), s->stream);
+        if (e == hipSuccess) e = launch_bias_reduce(cpart, k_chan[l + 1], G + b_off(l), s->stream);
         if (l == 0 || e != hipSuccess) break;
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
+        a.zc = conv_zc(s);
         a.in = dz;
         a.wpack = at<uint16_t>(s, s->L.wd[l]);
         a.zprev = at<uint16_t>(s, s->L.z[l - 1]);
