@@ -106,8 +106,10 @@ size_t gs_workspace_bytes(const gs_params *p);
 /* Tile shapes (valid gs_params.tile values are 1..gs_num_tiles()). The first
  * four select the single-step z-streaming kernel (tblock must be 1); the
  * others select the temporally blocked kernel, which fuses tblock steps per
- * pass. gs_tile_info reports the output tile (tx cells by ty rows) of `tile`
- * for a storage type and tblock, and the largest tblock the tile accepts. */
+ * pass (workgroups of 256 to 1024 lanes; the larger ones fuse fewer steps in
+ * FP64, whose registers are twice as many). gs_tile_info reports the output
+ * tile (tx cells by ty rows) of `tile` for a storage type and tblock, and the
+ * largest tblock the tile accepts for that storage type. */
 int32_t gs_num_tiles(void);
 gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t tblock, int32_t *tx, int32_t *ty,
                        int32_t *max_tblock);
@@ -214,6 +216,12 @@ typedef struct gs_batch_tune_entry {
     double ms_per_step;               /* time per step of all its simulations together */
     double gcells;                    /* their cell-updates per second, in units of 1e9 */
 } gs_batch_tune_entry;
+
+/* Largest tblock a temporally blocked tile accepts in batched sweeps for a
+ * storage type (the persistent kernel needs a few more registers than the
+ * single-grid one); 0 when the tile is not available to batches or the
+ * arguments are invalid. */
+int32_t gs_batch_max_tblock(int32_t tile, int32_t storage);
 
 /* Device bytes of the fields of all simulations (4 buffers each, 256-byte
  * aligned) and of the batch workspace (descriptors, work lists, diagnostic

@@ -55,6 +55,7 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // kernel's shapes (any tblock).
 int total_tiles() { return gs::num_tiles() + gs::num_tb_shapes(); }
 bool is_tb_tile(int tile) { return tile > gs::num_tiles(); }
+int tile_max_tblock(int tile, int storage) { return is_tb_tile(tile) ? gs::tb_max_T(tile - gs::num_tiles(), storage) : 1; }
 
 gs_status validate(const gs_params *p)
 {
@@ -87,6 +88,9 @@ gs_status validate(const gs_params *p)
         return fail(GS_ERR_INVALID_ARG, "tile %d outside [0, %d]", p->tile, total_tiles());
     if (p->tile >= 1 && p->tile <= gs::num_tiles() && p->tblock > 1)
         return fail(GS_ERR_INVALID_ARG, "tile %d is a single-step tile; tblock must be 0 or 1", p->tile);
+    if (p->tile >= 1 && p->tblock > tile_max_tblock(p->tile, p->storage))
+        return fail(GS_ERR_INVALID_ARG, "tile %d fuses at most %d steps for this storage type", p->tile,
+                    tile_max_tblock(p->tile, p->storage));
     if (p->zchunk < 0) return fail(GS_ERR_INVALID_ARG, "zchunk %d < 0", p->zchunk);
     if (p->reserved != 0) return fail(GS_ERR_INVALID_ARG, "reserved field must be 0");
     return GS_OK;
@@ -233,7 +237,9 @@ int default_tile(const gs_params &p)
 int default_tblock(const gs_params &p, int tile)
 {
     if (tile <= gs::num_tiles()) return 1;
-    return (p.storage == GS_F64 || p.storage == GS_F32) ? 3 : 1;
+    const int T = (p.storage == GS_F64 || p.storage == GS_F32) ? 3 : 1;
+    const int mt = tile_max_tblock(tile, p.storage);
+    return T < mt ? T : mt;
 }
 
 int default_zc(const gs_params &p, int tile)
@@ -307,8 +313,6 @@ void drop_graph(gs_sim *s)
     s->graph = GraphCache();
 }
 
-int tile_max_tblock(int tile) { return is_tb_tile(tile) ? GS_MAX_TBLOCK : 1; }
-
 } // namespace
 
 extern "C" {
@@ -331,7 +335,7 @@ gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t tblock, int32_t *t
 {
     if (tile < 1 || tile > total_tiles()) return fail(GS_ERR_INVALID_ARG, "tile %d out of range", tile);
     if (storage_bytes(storage) == 0) return fail(GS_ERR_INVALID_ARG, "unknown storage type %d", storage);
-    const int mt = is_tb_tile(tile) ? GS_MAX_TBLOCK : 1;
+    const int mt = tile_max_tblock(tile, storage);
     if (tblock < 1 || tblock > mt) return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, mt, tile);
     gs::TileShape t = is_tb_tile(tile) ? gs::tb_shape(tile - gs::num_tiles(), tblock) : gs::tile_shape(tile, storage);
     if (tx) *tx = t.tx;
@@ -478,8 +482,8 @@ gs_status gs_set_config(gs_sim *s, int32_t tile, int32_t tblock, int32_t zchunk)
     gs_status st = check(s);
     if (st != GS_OK) return st;
     if (tile < 1 || tile > total_tiles()) return fail(GS_ERR_INVALID_ARG, "tile %d out of range", tile);
-    if (tblock < 1 || tblock > tile_max_tblock(tile))
-        return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, tile_max_tblock(tile), tile);
+    const int mt = tile_max_tblock(tile, s->p.storage);
+    if (tblock < 1 || tblock > mt) return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, mt, tile);
     if (zchunk < 1) return fail(GS_ERR_INVALID_ARG, "zchunk %d < 1", zchunk);
     s->tile = tile;
     s->tblock = tblock;
@@ -516,7 +520,7 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
     int bt = save_tile, bT = save_tb, bz = save_zc;
     int count = 0;
     for (int tile = 1; tile <= total_tiles() && e == hipSuccess; ++tile) {
-        for (int T = 1; T <= tile_max_tblock(tile) && e == hipSuccess; ++T) {
+        for (int T = 1; T <= tile_max_tblock(tile, s->p.storage) && e == hipSuccess; ++T) {
             int last_zc = -1;
             for (int zi = 0; zi < (int)(sizeof zcs / sizeof zcs[0]) && e == hipSuccess; ++zi) {
                 const int zc = zcs[zi] < s->p.nz ? zcs[zi] : s->p.nz;

@@ -306,6 +306,11 @@ gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx
     if (base->tile > gs::num_tiles() + gs::num_tb_shapes() || base->tile < 0)
         return fail(GS_ERR_INVALID_ARG, "tile %d out of range", base->tile);
     if (base->tblock < 0 || base->tblock > GS_MAX_TBLOCK) return fail(GS_ERR_INVALID_ARG, "tblock out of range");
+    if (gs::tb_batch_max_T(base->tile ? base->tile - gs::num_tiles() : 2, base->storage) < 1)
+        return fail(GS_ERR_UNSUPPORTED, "tile %d is not available to batched sweeps of this storage type", base->tile);
+    if (base->tblock > gs::tb_batch_max_T(base->tile ? base->tile - gs::num_tiles() : 2, base->storage))
+        return fail(GS_ERR_INVALID_ARG, "tile %d fuses at most %d steps for this storage type", base->tile,
+                    gs::tb_batch_max_T(base->tile ? base->tile - gs::num_tiles() : 2, base->storage));
     if (base->zchunk != 0 && base->zchunk < k_min_batch_zc)
         return fail(GS_ERR_INVALID_ARG, "batched zchunk must be 0 or >= %d", k_min_batch_zc);
     const size_t need_arena = gs_batch_arena_bytes(base->storage, n_sims, nx, ny, nz);
@@ -341,7 +346,9 @@ gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx
     }
     const size_t es = storage_bytes(base->storage);
     const int shape = base->tile ? base->tile - gs::num_tiles() : 2;
-    const int T = base->tblock ? base->tblock : ((base->storage == GS_F64 || base->storage == GS_F32) ? 3 : 1);
+    const int T = base->tblock ? base->tblock
+                               : std::min(gs::tb_batch_max_T(shape, base->storage),
+                                          (base->storage == GS_F64 || base->storage == GS_F32) ? 3 : 1);
     char *p = (char *)arena;
     for (int32_t i = 0; i < n_sims; ++i) {
         BSim s;
@@ -384,6 +391,13 @@ gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx
     return GS_OK;
 }
 
+int32_t gs_batch_max_tblock(int32_t tile, int32_t storage)
+{
+    if (tile <= gs::num_tiles() || tile > gs::num_tiles() + gs::num_tb_shapes()) return 0;
+    if (storage < GS_F64 || storage > GS_F16) return 0;
+    return gs::tb_batch_max_T(tile - gs::num_tiles(), storage);
+}
+
 gs_status gs_batch_set_config(gs_batch *b, int32_t sim, int32_t tile, int32_t tblock, int32_t zchunk)
 {
     gs_status st = bcheck(b);
@@ -392,7 +406,8 @@ gs_status gs_batch_set_config(gs_batch *b, int32_t sim, int32_t tile, int32_t tb
     if (tile <= gs::num_tiles() || tile > gs::num_tiles() + gs::num_tb_shapes())
         return fail(GS_ERR_INVALID_ARG, "batched tile must be in %d..%d", gs::num_tiles() + 1,
                     gs::num_tiles() + gs::num_tb_shapes());
-    if (tblock < 1 || tblock > GS_MAX_TBLOCK) return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d]", tblock, GS_MAX_TBLOCK);
+    const int mt = gs::tb_batch_max_T(tile - gs::num_tiles(), b->base.storage);
+    if (tblock < 1 || tblock > mt) return fail(GS_ERR_INVALID_ARG, "tblock %d outside [1, %d] for tile %d", tblock, mt, tile);
     if (zchunk < k_min_batch_zc) return fail(GS_ERR_INVALID_ARG, "zchunk %d < %d", zchunk, k_min_batch_zc);
     for (size_t i = 0; i < b->sims.size(); ++i) {
         if (sim != -1 && (int32_t)i != sim) continue;
@@ -528,7 +543,7 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
         double best = 1e300;
         int bs = b->sims[members[0]].shape, bT = b->sims[members[0]].T, bz = b->sims[members[0]].zc;
         for (int shape = 1; shape <= gs::num_tb_shapes() && e == hipSuccess; ++shape) {
-            for (int T = 1; T <= GS_MAX_TBLOCK && e == hipSuccess; ++T) {
+            for (int T = 1; T <= gs::tb_batch_max_T(shape, b->base.storage) && e == hipSuccess; ++T) {
                 int last = -1;
                 for (int zi = 0; zi < 4 && e == hipSuccess; ++zi) {
                     const int zc = std::min(zcs[zi], k.nz);

@@ -71,6 +71,13 @@ struct Philox4 {
     uint32_t w[4];
 };
 
+// a ^ b ^ c in one instruction (gfx950 three-input bit operation; truth
+// table 0x96 is the odd-parity function).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                  uint32_t k0, uint32_t k1)
 {
@@ -79,9 +86,9 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
         // One 32x32 -> 64-bit multiply instruction per product (hi and lo together).
         const uint64_t pa = (uint64_t)0xD2511F53u * c0;
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
-        c0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        c0 = xor3((uint32_t)(pb >> 32), c1, k0);
         c1 = (uint32_t)pb;
-        c2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c3 = (uint32_t)pa;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

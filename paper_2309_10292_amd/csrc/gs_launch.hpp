@@ -85,6 +85,12 @@ namespace gs {
 // tile shape 1..num_tb_shapes().
 int num_tb_shapes();
 TileShape tb_shape(int shape, int T);
+// Largest number of fused steps the temporally blocked shape runs for a
+// storage type (its registers fit the shape's lanes without spills), in the
+// single-grid kernel and in the persistent batched kernel (0: the shape is
+// not available).
+int tb_max_T(int shape, int storage);
+int tb_batch_max_T(int shape, int storage);
 hipError_t launch_tblock(int storage, int T, int shape, const void *u, const void *v, void *un, void *vn,
                          const StepArgs &a, hipStream_t st);
 

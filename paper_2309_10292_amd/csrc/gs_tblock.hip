@@ -7,15 +7,17 @@
 // is the state after k of the T steps; level k is needed on the output tile
 // widened by T - k rows in y and by one x-group on each side in x (enough for
 // T <= 4). Every lane owns one x-group of the level-0 region and the same
-// position in every level; a level is computed only where that position lies
-// in its region.
+// position in every level. The depth of a position is the last level that
+// needs it; lanes are ordered by decreasing depth, so a wave whose positions
+// are all shallower than level k skips level k as a whole.
 //
 // Per z iteration i (a wavefront in z):
 //   - level-0 plane i+1 enters (prefetched one iteration earlier);
 //   - for k = 1..T, level k computes plane i-k+1 from level k-1's planes
-//     i-k, i-k+1, i-k+2: z neighbours from the lane's registers (a 3-plane
-//     window per level), x and y neighbours from level k-1's current plane
-//     staged in LDS;
+//     i-k, i-k+1, i-k+2: z neighbours from the lane's registers (three plane
+//     slots per level; plane z sits in slot (z - i0) mod 3, and the loop is
+//     unrolled by three so that slots are fixed registers), x and y neighbours
+//     from level k-1's current plane staged in LDS;
 //   - level T's plane is stored if it lies in the workgroup's chunk;
 //   - each level's newest plane is staged in LDS for the next iteration.
 // Cells are evaluated by the same operation sequence as the single-step
@@ -77,6 +79,12 @@ template <> struct NtStore<f16> {
     }
 };
 
+template <int P> struct Phase {
+    static constexpr int value = P;
+};
+// Slot of a plane whose offset from the first loop plane is p (any sign).
+__host__ __device__ constexpr int slot3(int p) { return ((p % 3) + 3) % 3; }
+
 template <typename C>
 __device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, bool noisy, C r, C &uo, C &vo)
 {
@@ -104,19 +112,42 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * (size_t)ny;
 
-    // This lane's position: x-group gxs, level-0 row rys.
-    const int s = threadIdx.x;
-    const bool has = s < G::NSLOT;
-    const int gxs = s % G::GX;
-    const int rys = has ? s / G::GX : 0;
+    // This lane's position (x-group gxs, level-0 row rys) and depth dep
+    // (-1: none). Order: the output tile (depth T, row-major), the x-halo
+    // groups beside the output rows (depth T-1), then rows d and RY0-1-d for
+    // d = T-1 down to 0 (depth d).
+    int gxs = 0, rys = 0, dep = -1;
+    {
+        constexpr int nA = TXG * TY, nH = 2 * TY;
+        const int s = threadIdx.x;
+        if (s < nA) {
+            rys = T + s / TXG;
+            gxs = 1 + s % TXG;
+            dep = T;
+        } else if (s < nA + nH) {
+            const int r = s - nA;
+            rys = T + (r >> 1);
+            gxs = (r & 1) ? G::GX - 1 : 0;
+            dep = T - 1;
+        } else {
+            const int r = s - nA - nH;
+            const int d = T - 1 - r / (2 * G::GX);
+            if (d >= 0) {
+                const int q = r % (2 * G::GX);
+                rys = q < G::GX ? d : G::RY0 - 1 - d;
+                gxs = q % G::GX;
+                dep = d;
+            }
+        }
+    }
+    const bool has = dep >= 0;
     const int gx = (((x0 - 4 + 4 * gxs) % nx) + nx) % nx;
     const int gy = (((y0 - T + rys) % ny) + ny) % ny;
     const size_t xy = (size_t)gy * nx + gx;
-    // Output position (level T) and whether this lane stores it.
-    const bool out_slot = has && gxs >= 1 && gxs <= TXG && rys >= T && rys < T + TY;
-    const bool out_ok = out_slot && (x0 + 4 * (gxs - 1) < nx) && (y0 + rys - T < ny);
+    // Output positions are exactly the depth-T ones.
+    const bool out_ok = dep == T && (x0 + 4 * (gxs - 1) < nx) && (y0 + rys - T < ny);
 
-    C win[T][3][2][4]; // [level][m, c, p][field][cell]
+    C win[T][3][2][4]; // [level][slot][field][cell]
 #pragma unroll
     for (int k = 0; k < T; ++k)
 #pragma unroll
@@ -135,107 +166,98 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
     auto lds_at = [&](int f, int k, int row, int col) -> C & {
         return lds[f * G::FIELD + (G::row_base(k) + row) * G::RS + G::H + col];
     };
-    auto in_level = [&](int k) { return has && rys >= k && rys < G::RY0 - k; };
+    auto in_level = [&](int k) { return dep >= k; };
 
-    // Prologue: level-0 window holds planes z0-T, z0-T+1, z0-T+2; LDS holds z0-T+1.
+    // Prologue: level-0 slots hold planes i0-1 (slot 2) and i0 (slot 0); plane
+    // i0+1 is in flight; LDS holds level-0 plane i0.
     const int i0 = z0 - T + 1;
     const int i_end = ze + T - 2; // inclusive
     Vec<S, 4> pre[2];
     if (has) {
-        Vec<S, 4> t0[2], t1[2];
-        load_plane(i0 - 1, t0);
-        load_plane(i0, t1);
+        Vec<S, 4> q0[2], q1[2];
+        load_plane(i0 - 1, q0);
+        load_plane(i0, q1);
         load_plane(i0 + 1, pre);
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                win[0][1][f][e] = Traits<S>::load(t0[f].e[e]);
-                win[0][2][f][e] = Traits<S>::load(t1[f].e[e]);
+                win[0][2][f][e] = Traits<S>::load(q0[f].e[e]);
+                win[0][0][f][e] = Traits<S>::load(q1[f].e[e]);
             }
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][2][f][e];
+            for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][0][f][e];
     }
     __syncthreads();
 
-    for (int i = i0; i <= i_end; ++i) {
-        // Level 0: plane i+1 enters the window; prefetch plane i+2.
+    // One z iteration at phase P = (i - i0) mod 3.
+    auto iteration = [&](const int i, auto phase) {
+        constexpr int P = decltype(phase)::value;
+        // Level 0: plane i+1 enters its slot; prefetch plane i+2.
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                win[0][0][f][e] = win[0][1][f][e];
-                win[0][1][f][e] = win[0][2][f][e];
-                win[0][2][f][e] = Traits<S>::load(pre[f].e[e]);
-            }
+            for (int e = 0; e < 4; ++e) win[0][slot3(P + 1)][f][e] = Traits<S>::load(pre[f].e[e]);
         if (has && i + 2 <= ze + T - 1) load_plane(i + 2, pre);
 
         // Levels 1..T, in order; level k computes plane i-k+1.
 #pragma unroll
         for (int k = 1; k <= T; ++k) {
+            if (!in_level(k)) continue;
             const int zk = i - k + 1;
-            C res[2][4];
-            if (in_level(k)) {
-                const int row = rys - (k - 1); // row of this position in level k-1's LDS plane
-                C xm[2][4], xp[2][4], ym[2][4], yp[2][4];
+            const int sm = slot3(P - k), sc = slot3(P - k + 1), sp = slot3(P - k + 2);
+            const int row = rys - (k - 1); // row of this position in level k-1's LDS plane
+            C xm[2][4], xp[2][4], ym[2][4], yp[2][4];
 #pragma unroll
-                for (int f = 0; f < 2; ++f) {
-                    const C *c = win[k - 1][1][f];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        xm[f][e] = e > 0 ? c[e - 1] : lds_at(f, k - 1, row, 4 * gxs - 1);
-                        xp[f][e] = e < 3 ? c[e + 1] : lds_at(f, k - 1, row, 4 * gxs + 4);
-                        ym[f][e] = lds_at(f, k - 1, row - 1, 4 * gxs + e);
-                        yp[f][e] = lds_at(f, k - 1, row + 1, 4 * gxs + e);
-                    }
-                }
-                C r[4] = {(C)0, (C)0, (C)0, (C)0};
-                if constexpr (NOISE) {
-                    const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
-                    const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if constexpr (sizeof(C) == 8)
-                            r[e] = noise_word_f64(w.w[e]);
-                        else
-                            r[e] = noise_word_f32(w.w[e]);
-                    }
-                }
+            for (int f = 0; f < 2; ++f) {
+                const C *c = win[k - 1][sc][f];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const C uc = win[k - 1][1][0][e], vc = win[k - 1][1][1][e];
-                    C lu, lv;
-                    if constexpr (sizeof(C) == 8) {
-                        lu = lap_f64(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][0][0][e], win[k - 1][2][0][e]);
-                        lv = lap_f64(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][0][1][e], win[k - 1][2][1][e]);
-                    } else {
-                        lu = lap_comp_f32(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][0][0][e], win[k - 1][2][0][e]);
-                        lv = lap_comp_f32(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][0][1][e], win[k - 1][2][1][e]);
-                    }
-                    C uo, vo;
-                    cell_update<C>(a, uc, vc, lu, lv, NOISE, r[e], uo, vo);
-                    // Intermediate levels carry the stored precision of the state.
-                    res[0][e] = Traits<S>::load(Traits<S>::store(uo));
-                    res[1][e] = Traits<S>::load(Traits<S>::store(vo));
+                    xm[f][e] = e > 0 ? c[e - 1] : lds_at(f, k - 1, row, 4 * gxs - 1);
+                    xp[f][e] = e < 3 ? c[e + 1] : lds_at(f, k - 1, row, 4 * gxs + 4);
+                    ym[f][e] = lds_at(f, k - 1, row - 1, 4 * gxs + e);
+                    yp[f][e] = lds_at(f, k - 1, row + 1, 4 * gxs + e);
                 }
-            } else {
+            }
+            C r[4] = {(C)0, (C)0, (C)0, (C)0};
+            if constexpr (NOISE) {
+                const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
+                const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
 #pragma unroll
-                for (int f = 0; f < 2; ++f)
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (sizeof(C) == 8)
+                        r[e] = noise_word_f64(w.w[e]);
+                    else
+                        r[e] = noise_word_f32(w.w[e]);
+                }
+            }
+            C res[2][4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) res[f][e] = (C)0;
+            for (int e = 0; e < 4; ++e) {
+                const C uc = win[k - 1][sc][0][e], vc = win[k - 1][sc][1][e];
+                C lu, lv;
+                if constexpr (sizeof(C) == 8) {
+                    lu = lap_f64(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][sm][0][e], win[k - 1][sp][0][e]);
+                    lv = lap_f64(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][sm][1][e], win[k - 1][sp][1][e]);
+                } else {
+                    lu = lap_comp_f32(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][sm][0][e],
+                                      win[k - 1][sp][0][e]);
+                    lv = lap_comp_f32(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][sm][1][e],
+                                      win[k - 1][sp][1][e]);
+                }
+                C uo, vo;
+                cell_update<C>(a, uc, vc, lu, lv, NOISE, r[e], uo, vo);
+                // Intermediate levels carry the stored precision of the state.
+                res[0][e] = Traits<S>::load(Traits<S>::store(uo));
+                res[1][e] = Traits<S>::load(Traits<S>::store(vo));
             }
             if (k < T) {
-                // Rotate level k's window: the new plane becomes 'p'.
 #pragma unroll
                 for (int f = 0; f < 2; ++f)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        win[k][0][f][e] = win[k][1][f][e];
-                        win[k][1][f][e] = win[k][2][f][e];
-                        win[k][2][f][e] = res[f][e];
-                    }
+                    for (int e = 0; e < 4; ++e) win[k][sc][f][e] = res[f][e];
             } else if (out_ok && zk >= z0) {
                 Vec<S, 4> ou, ov;
 #pragma unroll
@@ -254,7 +276,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
             for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][2][f][e];
+                for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][slot3(P + 1)][f][e];
         }
 #pragma unroll
         for (int k = 1; k < T; ++k) {
@@ -262,10 +284,16 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
                 for (int f = 0; f < 2; ++f)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, 4 * gxs + e) = win[k][2][f][e];
+                    for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, 4 * gxs + e) = win[k][slot3(P - k + 1)][f][e];
             }
         }
         __syncthreads();
+    };
+
+    for (int i = i0; i <= i_end; i += 3) {
+        iteration(i, Phase<0>{});
+        if (i + 1 <= i_end) iteration(i + 1, Phase<1>{});
+        if (i + 2 <= i_end) iteration(i + 2, Phase<2>{});
     }
 }
 
@@ -337,9 +365,29 @@ static hipError_t launch_tb_t(const void *u, const void *v, void *un, void *vn, 
 
 // Shapes per T (output x-groups, rows, lanes): the level-0 region
 // (TXG + 2) x (TY + 2T) fills the workgroup.
-//   shape 1: TXG=16, 256 lanes, region 18 x 14
-//   shape 2: TXG=16, 512 lanes, region 18 x 28
-//   shape 3: TXG=32, 512 lanes, region 34 x 14
+//   shape 1: TXG=16,  256 lanes, region 18 x 14
+//   shape 2: TXG=16,  512 lanes, region 18 x 28
+//   shape 3: TXG=32,  512 lanes, region 34 x 14
+//   shape 4: TXG=16,  768 lanes, region 18 x 42
+//   shape 5: TXG=16, 1024 lanes, region 18 x 56
+// One workgroup per CU: NT lanes leave 512 / ceil(NT / 256) registers per
+// lane. The deepest fusion whose registers fit that budget without spills
+// (the persistent batched kernel holds a few more registers for its work
+// list):
+template <typename S, int NT, bool BATCH> constexpr int tb_max_T_of()
+{
+    if (NT <= 512) return 4;
+    if (NT <= 768) return sizeof(S) == 8 ? (BATCH ? 1 : 2) : 4;
+    return sizeof(S) == 8 ? (BATCH ? 0 : 1) : (BATCH ? 2 : 3);
+}
+constexpr int shape_lanes(int shape) { return shape == 1 ? 256 : shape <= 3 ? 512 : shape == 4 ? 768 : 1024; }
+template <typename S, bool BATCH> constexpr int tb_max_T_shape(int shape)
+{
+    return shape <= 3   ? tb_max_T_of<S, 512, BATCH>()
+           : shape == 4 ? tb_max_T_of<S, 768, BATCH>()
+                        : tb_max_T_of<S, 1024, BATCH>();
+}
+
 template <typename S, int T>
 static hipError_t dispatch_tb_shape(int shape, const void *u, const void *v, void *un, void *vn, const StepArgs &a,
                                     hipStream_t st)
@@ -348,6 +396,14 @@ static hipError_t dispatch_tb_shape(int shape, const void *u, const void *v, voi
     case 1: return launch_tb_t<S, 16, 14 - 2 * T, T, 256>(u, v, un, vn, a, st);
     case 2: return launch_tb_t<S, 16, 28 - 2 * T, T, 512>(u, v, un, vn, a, st);
     case 3: return launch_tb_t<S, 32, 14 - 2 * T, T, 512>(u, v, un, vn, a, st);
+    case 4:
+        if constexpr (T <= tb_max_T_of<S, 768, false>())
+            return launch_tb_t<S, 16, 42 - 2 * T, T, 768>(u, v, un, vn, a, st);
+        break;
+    case 5:
+        if constexpr (T <= tb_max_T_of<S, 1024, false>())
+            return launch_tb_t<S, 16, 56 - 2 * T, T, 1024>(u, v, un, vn, a, st);
+        break;
     }
     return hipErrorInvalidValue;
 }
@@ -365,7 +421,7 @@ static hipError_t dispatch_tb_T(int T, int shape, const void *u, const void *v, 
     return hipErrorInvalidValue;
 }
 
-int num_tb_shapes() { return 3; }
+int num_tb_shapes() { return 5; }
 
 TileShape tb_shape(int shape, int T)
 {
@@ -373,9 +429,26 @@ TileShape tb_shape(int shape, int T)
     case 1: return TileShape{64, 14 - 2 * T};
     case 2: return TileShape{64, 28 - 2 * T};
     case 3: return TileShape{128, 14 - 2 * T};
+    case 4: return TileShape{64, 42 - 2 * T};
+    case 5: return TileShape{64, 56 - 2 * T};
     }
     return TileShape{0, 0};
 }
+
+template <bool BATCH> static int max_T_for(int shape, int storage)
+{
+    if (shape < 1 || shape > 5) return 0;
+    switch (storage) {
+    case 0: return tb_max_T_shape<double, BATCH>(shape);
+    case 1: return tb_max_T_shape<float, BATCH>(shape);
+    case 2: return tb_max_T_shape<bf16, BATCH>(shape);
+    case 3: return tb_max_T_shape<f16, BATCH>(shape);
+    }
+    return 0;
+}
+
+int tb_max_T(int shape, int storage) { return max_T_for<false>(shape, storage); }
+int tb_batch_max_T(int shape, int storage) { return max_T_for<true>(shape, storage); }
 
 template <typename S, int TXG, int TY, int T, int NT>
 static hipError_t launch_tb_batch_t(const BatchArgs &b, int grid, hipStream_t st)
@@ -395,6 +468,13 @@ static hipError_t batch_shape(int shape, const BatchArgs &b, int grid, hipStream
     case 1: return launch_tb_batch_t<S, 16, 14 - 2 * T, T, 256>(b, grid, st);
     case 2: return launch_tb_batch_t<S, 16, 28 - 2 * T, T, 512>(b, grid, st);
     case 3: return launch_tb_batch_t<S, 32, 14 - 2 * T, T, 512>(b, grid, st);
+    case 4:
+        if constexpr (T <= tb_max_T_of<S, 768, true>()) return launch_tb_batch_t<S, 16, 42 - 2 * T, T, 768>(b, grid, st);
+        break;
+    case 5:
+        if constexpr (T <= tb_max_T_of<S, 1024, true>())
+            return launch_tb_batch_t<S, 16, 56 - 2 * T, T, 1024>(b, grid, st);
+        break;
     }
     return hipErrorInvalidValue;
 }
@@ -422,7 +502,7 @@ hipError_t launch_tblock_batch(int storage, int T, int shape, const BatchArgs &b
     return hipErrorInvalidValue;
 }
 
-int tb_shape_lanes(int shape) { return shape == 1 ? 256 : 512; }
+int tb_shape_lanes(int shape) { return shape_lanes(shape); }
 
 template <typename S, int TXG, int TY, int T, int NT>
 static int occ_t()
@@ -440,6 +520,12 @@ static int occ_shape(int shape)
     case 1: return occ_t<S, 16, 14 - 2 * T, T, 256>();
     case 2: return occ_t<S, 16, 28 - 2 * T, T, 512>();
     case 3: return occ_t<S, 32, 14 - 2 * T, T, 512>();
+    case 4:
+        if constexpr (T <= tb_max_T_of<S, 768, true>()) return occ_t<S, 16, 42 - 2 * T, T, 768>();
+        break;
+    case 5:
+        if constexpr (T <= tb_max_T_of<S, 1024, true>()) return occ_t<S, 16, 56 - 2 * T, T, 1024>();
+        break;
     }
     return 1;
 }

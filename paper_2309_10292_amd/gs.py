@@ -92,6 +92,7 @@ SIGNATURES = [
     ("gs_batch_set_config", _I32, [_SIM, _I32, _I32, _I32, _I32]),
     ("gs_batch_get_config", _I32, [_SIM, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("gs_batch_tune", _I32, [_SIM, _I32, ctypes.c_void_p, _I32, ctypes.POINTER(_I32)]),
+    ("gs_batch_max_tblock", _I32, [_I32, _I32]),
     ("gs_batch_current", _I32, [_SIM, _I32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_uint64)]),
     ("gs_batch_read", _I32, [_SIM, _I32, _DP, _DP]),
     ("gs_batch_write", _I32, [_SIM, _I32, _DP, _DP]),
@@ -168,6 +169,24 @@ def _stream_handle(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def max_tblock(tile: int, storage="f64", batch: bool = False) -> int:
+    """Largest fused depth `tile` accepts for a storage type (0: not available)."""
+    st = DTYPES[storage] if isinstance(storage, str) else int(storage)
+    L = load()
+    if batch:
+        return int(L.gs_batch_max_tblock(int(tile), st))
+    mt = ctypes.c_int32()
+    if L.gs_tile_info(int(tile), st, 1, None, None, ctypes.byref(mt)) != GS_OK:
+        return 0
+    return int(mt.value)
+
+
+def tblock_tiles():
+    """Tile indices of the temporally blocked kernel (the first four tiles
+    select the single-step kernel)."""
+    return list(range(5, int(load().gs_num_tiles()) + 1))
 
 
 class Sim:

@@ -141,3 +141,16 @@ def test_workspace_and_tiles():
                 assert ty.value > 0
             assert L.gs_tile_info(t, s, mt.value + 1, None, None, None) == gs.GS_ERR_INVALID_ARG
     assert L.gs_tile_info(0, 0, 1, None, None, None) == gs.GS_ERR_INVALID_ARG
+
+
+def test_batch_max_tblock():
+    L = gs.load()
+    n = L.gs_num_tiles()
+    assert L.gs_batch_max_tblock(1, 0) == 0           # single-step tile
+    assert L.gs_batch_max_tblock(n + 1, 0) == 0       # out of range
+    assert L.gs_batch_max_tblock(5, 7) == 0           # unknown storage
+    for t in range(5, n + 1):
+        for s in range(4):
+            mb = L.gs_batch_max_tblock(t, s)
+            assert 0 <= mb <= gs.max_tblock(t, s) <= 4
+    assert gs.max_tblock(6, "f64") == 4 and gs.max_tblock(6, "f64", batch=True) == 4

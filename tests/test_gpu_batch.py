@@ -29,7 +29,9 @@ def test_batch_mixed_sizes_bitwise(torch):
     sims = [dict(nx=32, ny=32, nz=32, F=0.02, k=0.048), dict(nx=48, ny=40, nz=36, F=0.035, k=0.06),
             dict(nx=16, ny=20, nz=24, F=0.05, k=0.065), dict(nx=64, ny=24, nz=70, F=0.012, k=0.045)]
     for T in (1, 2, 3):
-        for tile in (5, 6, 7):
+        for tile in gs.tblock_tiles():
+            if T > gs.max_tblock(tile, "f64", batch=True):
+                continue
             with gs.Batch(sims, noise=1e-3, seed=100, cube_side=8, tile=tile, tblock=T, zchunk=16, **SHARED) as b:
                 b.step(7)
                 for i, sm in enumerate(sims):

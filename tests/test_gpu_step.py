@@ -250,7 +250,14 @@ def test_full_size_l1024_fp64_sampled(torch):
         del prev
 
 
-TB_TILES = (5, 6, 7)
+def tb_tiles():
+    from paper_2309_10292_amd import gs
+    return gs.tblock_tiles()
+
+
+def max_T(tile, storage):
+    from paper_2309_10292_amd import gs
+    return gs.max_tblock(tile, storage)
 
 
 @pytest.mark.parametrize("T", [1, 2, 3, 4])
@@ -263,7 +270,9 @@ def test_tblock_bitwise_vs_oracle(torch, T):
         p = dict(Du=0.19, Dv=0.11, F=0.029, k=0.055, dt=0.9, noise=0.01, seed=4242, step0=77)
         n = 2 * T + 1
         ue, ve = O.run(u0, v0, n, **p)
-        for tile in TB_TILES:
+        for tile in tb_tiles():
+            if T > max_T(tile, "f64"):
+                continue
             with _sim(shape, u0=u0, v0=v0, tile=tile, tblock=T, zchunk=16, **p) as s:
                 s.step(n)
                 u, v = s.read()
@@ -273,8 +282,10 @@ def test_tblock_bitwise_vs_oracle(torch, T):
 
 def test_tblock_small_l64_fp64_bitwise(torch, small_ref):
     p = workload("small_l64")
-    for T in (2, 4):
-        for tile in TB_TILES:
+    for T in (1, 2, 4):
+        for tile in tb_tiles():
+            if T > max_T(tile, "f64"):
+                continue
             with _sim((64, 64, 64), tile=tile, tblock=T, **P0) as s:
                 s.step(p["steps"])
                 u, v = s.read()
@@ -291,12 +302,13 @@ def test_tblock_reduced_precision_equals_single_step(torch, storage):
         s.step(9)
         ref = s.current()
         ref = (ref[0].clone(), ref[1].clone())
-    for T in (2, 3, 4):
-        with _sim(shape, storage=storage, tile=5, tblock=T, cube_side=10, **p) as s:
-            s.step(9)
-            u_t, v_t, st = s.current()
-            assert st == 9
-            assert torch.equal(u_t, ref[0]) and torch.equal(v_t, ref[1]), (storage, T)
+    for tile in tb_tiles():
+        for T in range(2, max_T(tile, storage) + 1):
+            with _sim(shape, storage=storage, tile=tile, tblock=T, cube_side=10, **p) as s:
+                s.step(9)
+                u_t, v_t, st = s.current()
+                assert st == 9
+                assert torch.equal(u_t, ref[0]) and torch.equal(v_t, ref[1]), (storage, tile, T)
 
 
 def test_tblock_full_size_l512_noise(torch):
