@@ -82,6 +82,9 @@ template <> struct NtStore<f16> {
 template <int P> struct Phase {
     static constexpr int value = P;
 };
+template <bool F> struct Full {
+    static constexpr bool value = F;
+};
 // Slot of a plane whose offset from the first loop plane is p (any sign).
 __host__ __device__ constexpr int slot3(int p) { return ((p % 3) + 3) % 3; }
 
@@ -102,7 +105,7 @@ __device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu,
 // (a.nx, a.ny, a.nz), T steps from (u, v) into (un, vn); t0 is the step index
 // of the first of the T steps. `lds` holds 2 * TbGeom::FIELD elements. Every
 // lane of the workgroup must call it (it contains barriers).
-template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
+template <typename S, int TXG, int TY, int T, int NT, bool NOISE, bool BATCH>
 __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__restrict__ v, S *__restrict__ un,
                                         S *__restrict__ vn, const StepArgs &a, int x0, int y0, int z0, int ze,
                                         uint64_t t0, typename Traits<S>::C *__restrict__ lds)
@@ -192,9 +195,16 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
     }
     __syncthreads();
 
-    // One z iteration at phase P = (i - i0) mod 3.
-    auto iteration = [&](const int i, auto phase) {
+    // One z iteration at phase P = (i - i0) mod 3. A wave whose first lane
+    // (the deepest position of the wave) has depth T runs every level on all
+    // of its lanes without per-lane branches (FULL): the lanes that a level
+    // does not need compute values nobody reads, from clamped LDS rows, and
+    // only the stores stay per-lane. Straight-line levels let the scheduler
+    // overlap the Philox chains with LDS reads and arithmetic. Other waves
+    // skip, per lane, the levels their positions do not need.
+    auto iteration = [&](const int i, auto phase, auto full) {
         constexpr int P = decltype(phase)::value;
+        constexpr bool FULL = decltype(full)::value;
         // Level 0: plane i+1 enters its slot; prefetch plane i+2.
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -205,10 +215,13 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
         // Levels 1..T, in order; level k computes plane i-k+1.
 #pragma unroll
         for (int k = 1; k <= T; ++k) {
-            if (!in_level(k)) continue;
+            if (!FULL && !in_level(k)) continue;
             const int zk = i - k + 1;
             const int sm = slot3(P - k), sc = slot3(P - k + 1), sp = slot3(P - k + 2);
-            const int row = rys - (k - 1); // row of this position in level k-1's LDS plane
+            // Row of this position in level k-1's LDS plane (clamped for
+            // positions outside level k, whose results are not used).
+            const int ry = FULL ? min(max(rys, k), G::RY0 - 1 - k) : rys;
+            const int row = ry - (k - 1);
             C xm[2][4], xp[2][4], ym[2][4], yp[2][4];
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
@@ -290,10 +303,23 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
         __syncthreads();
     };
 
-    for (int i = i0; i <= i_end; i += 3) {
-        iteration(i, Phase<0>{});
-        if (i + 1 <= i_end) iteration(i + 1, Phase<1>{});
-        if (i + 2 <= i_end) iteration(i + 2, Phase<2>{});
+    // The straight-line variant needs more registers; it is used where they
+    // fit the budget (up to 512 lanes; FP64 up to 3 levels, and not in the
+    // persistent batched kernel).
+    constexpr bool full_ok = NT <= 512 && (sizeof(C) == 4 || (T <= 3 && !BATCH));
+    const int wave_depth = __builtin_amdgcn_readfirstlane(dep);
+    if (full_ok && wave_depth == T) {
+        for (int i = i0; i <= i_end; i += 3) {
+            iteration(i, Phase<0>{}, Full<true>{});
+            if (i + 1 <= i_end) iteration(i + 1, Phase<1>{}, Full<true>{});
+            if (i + 2 <= i_end) iteration(i + 2, Phase<2>{}, Full<true>{});
+        }
+    } else {
+        for (int i = i0; i <= i_end; i += 3) {
+            iteration(i, Phase<0>{}, Full<false>{});
+            if (i + 1 <= i_end) iteration(i + 1, Phase<1>{}, Full<false>{});
+            if (i + 2 <= i_end) iteration(i + 2, Phase<2>{}, Full<false>{});
+        }
     }
 }
 
@@ -310,7 +336,8 @@ __global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const 
     const int bz = (int)(rest / (uint32_t)a.nty);
     const int z0 = bz * a.zc;
     const uint64_t t0 = NOISE ? step_index(a) : 0;
-    tb_tile<S, TXG, TY, T, NT, NOISE>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, min(z0 + a.zc, a.nz), t0, lds);
+    tb_tile<S, TXG, TY, T, NT, NOISE, false>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, min(z0 + a.zc, a.nz), t0,
+                                             lds);
 }
 
 // Persistent sweep over many independent simulations: each workgroup walks
@@ -340,7 +367,7 @@ __global__ __launch_bounds__(NT) void stencil_tb_batch(BatchArgs b)
         const S *v = (const S *)d.buf[b.parity][1];
         S *un = (S *)d.buf[b.parity ^ 1][0];
         S *vn = (S *)d.buf[b.parity ^ 1][1];
-        tb_tile<S, TXG, TY, T, NT, NOISE>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, min(z0 + d.zc, d.nz), t0,
+        tb_tile<S, TXG, TY, T, NT, NOISE, true>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, min(z0 + d.zc, d.nz), t0,
                                           lds);
     }
 }
@@ -377,7 +404,7 @@ static hipError_t launch_tb_t(const void *u, const void *v, void *un, void *vn, 
 template <typename S, int NT, bool BATCH> constexpr int tb_max_T_of()
 {
     if (NT <= 512) return 4;
-    if (NT <= 768) return sizeof(S) == 8 ? (BATCH ? 1 : 2) : 4;
+    if (NT <= 768) return sizeof(S) == 8 ? (BATCH ? 1 : 2) : (BATCH ? 3 : 4);
     return sizeof(S) == 8 ? (BATCH ? 0 : 1) : (BATCH ? 2 : 3);
 }
 constexpr int shape_lanes(int shape) { return shape == 1 ? 256 : shape <= 3 ? 512 : shape == 4 ? 768 : 1024; }
