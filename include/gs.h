@@ -276,7 +276,10 @@ gs_status gs_batch_destroy(gs_batch *b);
  * convolutions (channels 4 -> 32 -> 32 -> 32 -> 2, GELU after the first
  * three, bias everywhere) mapping (u, v, (F - 0.035) / 0.025, (k - 0.055) /
  * 0.015) to a correction added to (u, v). BF16 weights and activations, FP32
- * accumulation on the matrix cores, FP32 master weights for Adam.
+ * accumulation on the matrix cores, FP32 master weights for Adam. The network
+ * reads u and v as BF16 pairs (high part plus the BF16 rounding of the rest,
+ * about 16 significant bits) that share one weight, so the 16-step change it
+ * predicts is not swamped by BF16 rounding of fields near 1.
  * Parameters are a flat FP32 host array of GS_SURR_NPARAMS values: for each
  * layer W[c_out][c_in][3][3][3] (row-major; W[o][i][dz][dy][dx] multiplies
  * the input at (z + dz - 1, y + dy - 1, x + dx - 1), periodic), then b[c_out].

@@ -279,15 +279,19 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     }
 }
 
-// grad[W(co, ci, d)] = sum over workgroups of the partials (fixed order).
+// grad[W(co, ci, d)] = sum over workgroups of the partials (fixed order);
+// the first lo_pairs input channels add the partials of their low parts
+// (stored channels cin ..).
 __global__ __launch_bounds__(256) void wgrad_reduce(const float *__restrict__ part, int nblk, int pco, int pci,
-                                                    int cout, int cin, float *__restrict__ gW)
+                                                    int cout, int cin, int lo_pairs, float *__restrict__ gW)
 {
     const int n = cout * cin * 27;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int d = e % 27, ci = (e / 27) % cin, co = e / (27 * cin);
         double s = 0.0;
         for (int b = 0; b < nblk; ++b) s += part[(((size_t)b * 27 + d) * pco + co) * pci + ci];
+        if (ci < lo_pairs)
+            for (int b = 0; b < nblk; ++b) s += part[(((size_t)b * 27 + d) * pco + co) * pci + cin + ci];
         gW[e] = (float)s;
     }
 }
@@ -312,10 +316,15 @@ __global__ __launch_bounds__(256) void pack_input(const IO *__restrict__ u, cons
     const size_t rows = (size_t)nsamp * ncell;
     for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (size_t)gridDim.x * blockDim.x) {
         const int s = (int)(r / ncell);
+        // u and v as BF16 pairs hi + lo (about 16 significant bits); the first
+        // layer applies the same weight to both parts.
+        const float uf = (float)u[r], vf = (float)v[r];
+        const u16 uh = f2bf(uf), vh = f2bf(vf);
+        const u16 ul = f2bf(uf - bf2f(uh)), vl = f2bf(vf - bf2f(vh));
         uint4 q;
-        q.x = (uint32_t)f2bf((float)u[r]) | ((uint32_t)f2bf((float)v[r]) << 16);
+        q.x = (uint32_t)uh | ((uint32_t)vh << 16);
         q.y = (uint32_t)f2bf((fk[2 * s] - F_CENTER) / F_SCALE) | ((uint32_t)f2bf((fk[2 * s + 1] - K_CENTER) / K_SCALE) << 16);
-        q.z = 0u;
+        q.z = (uint32_t)ul | ((uint32_t)vl << 16);
         q.w = 0u;
         *reinterpret_cast<uint4 *>(x + r * 8) = q;
     }
@@ -365,8 +374,10 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
 // convolution kernel: chunk c, N-tile t, lane, 8 consecutive k = 32 c + 8
 // (lane / 16) + j with k = d * cins + ci. DGRAD packs the mirrored, transposed
 // weights W'[ci][co][d] = W[co][ci][26 - d] (input channels = co).
+// lo_pairs: input channels cin .. cin + lo_pairs - 1 carry the low parts of
+// channels 0 .. lo_pairs - 1 and take their weights.
 __global__ __launch_bounds__(256) void repack(const float *__restrict__ W, int cout, int cin, int cins, int nt,
-                                              int nch, int dgrad, u16 *__restrict__ out)
+                                              int nch, int dgrad, int lo_pairs, u16 *__restrict__ out)
 {
     const int total = nch * nt * 64 * 8;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
@@ -376,7 +387,8 @@ __global__ __launch_bounds__(256) void repack(const float *__restrict__ W, int c
         float w = 0.f;
         if (d < 27) {
             if (!dgrad) {
-                if (kc < cin && n < cout) w = W[((size_t)n * cin + kc) * 27 + d];
+                const int src = kc < cin ? kc : (kc - cin < lo_pairs ? kc - cin : -1);
+                if (src >= 0 && n < cout) w = W[((size_t)n * cin + src) * 27 + d];
             } else {
                 // input channel kc = co of the layer, output channel n = ci of the layer
                 if (kc < cout && n < cin) w = W[((size_t)kc * cin + n) * 27 + (26 - d)];
@@ -429,11 +441,12 @@ hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, float *gW, hipStream_t st)
+hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, int lo_pairs, float *gW,
+                               hipStream_t st)
 {
     const int n = cout * cin * 27;
     hipLaunchKernelGGL(wgrad_reduce, dim3(grid_cap(n, 256, 1024)), dim3(256), 0, st, part, wgrad_blocks(), pco, pci,
-                       cout, cin, gW);
+                       cout, cin, lo_pairs, gW);
     return hipGetLastError();
 }
 
@@ -473,12 +486,12 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, floa
     return hipGetLastError();
 }
 
-hipError_t launch_repack(const float *W, int cout, int cin, int cins, int nt, int nch, int dgrad, uint16_t *out,
-                         hipStream_t st)
+hipError_t launch_repack(const float *W, int cout, int cin, int cins, int nt, int nch, int dgrad, int lo_pairs,
+                         uint16_t *out, hipStream_t st)
 {
     const int total = nch * nt * 512;
     hipLaunchKernelGGL(repack, dim3(grid_cap(total, 256, 1024)), dim3(256), 0, st, W, cout, cin, cins, nt, nch, dgrad,
-                       out);
+                       lo_pairs, out);
     return hipGetLastError();
 }
 

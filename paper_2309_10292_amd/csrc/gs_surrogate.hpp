@@ -45,7 +45,8 @@ struct WgradArgs {
 hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a, hipStream_t st);
 int wgrad_blocks();
 hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st);
-hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, float *gW, hipStream_t st);
+hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, int cin, int lo_pairs, float *gW,
+                               hipStream_t st);
 hipError_t launch_bias_reduce(const float *bpart, int cout, float *gb, hipStream_t st);
 hipError_t launch_pack_input(int io_f64, const void *u, const void *v, const float *fk, int nsamp, int ncell,
                              uint16_t *x, hipStream_t st);
@@ -54,8 +55,8 @@ hipError_t launch_loss_grad(const float *pu, const float *pv, const float *tu, c
                             float scale, uint16_t *dz4, double *part, hipStream_t st);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
                        float c1, float c2, hipStream_t st);
-hipError_t launch_repack(const float *W, int cout, int cin, int cins, int nt, int nch, int dgrad, uint16_t *out,
-                         hipStream_t st);
+hipError_t launch_repack(const float *W, int cout, int cin, int cins, int nt, int nch, int dgrad, int lo_pairs,
+                         uint16_t *out, hipStream_t st);
 
 } // namespace nn
 } // namespace gs

@@ -20,6 +20,9 @@ const uint32_t k_surr_magic = 0x47535347u; // "GSSG"
 const int k_chan[5] = {4, 32, 32, 32, 2};  // real channels per layer boundary
 const int k_cins[4] = {8, 32, 32, 32};     // stored input channels of layers 1..4
 const int k_nt[4] = {2, 2, 2, 1};          // 16-wide output tiles of layers 1..4
+// The input stores (u_hi, v_hi, f, k, u_lo, v_lo, 0, 0): u and v as BF16
+// pairs whose low parts share the weights of the high parts.
+const int k_lo_pairs = 2;
 
 int nchunks(int cins) { return (27 * cins + 31) / 32; }
 
@@ -113,10 +116,10 @@ hipError_t repack_all(gs_surrogate *s)
     hipError_t e = hipSuccess;
     for (int l = 0; l < 4 && e == hipSuccess; ++l)
         e = gs::nn::launch_repack(P + w_off(l), k_chan[l + 1], k_chan[l], k_cins[l], k_nt[l], nchunks(k_cins[l]), 0,
-                                  at<uint16_t>(s, s->L.wf[l]), s->stream);
+                                  l == 0 ? k_lo_pairs : 0, at<uint16_t>(s, s->L.wf[l]), s->stream);
     for (int l = 1; l < 4 && e == hipSuccess; ++l) {
         const int cins = l == 3 ? 8 : 32;
-        e = gs::nn::launch_repack(P + w_off(l), k_chan[l + 1], k_chan[l], cins, 2, nchunks(cins), 1,
+        e = gs::nn::launch_repack(P + w_off(l), k_chan[l + 1], k_chan[l], cins, 2, nchunks(cins), 1, 0,
                                   at<uint16_t>(s, s->L.wd[l]), s->stream);
     }
     return e;
@@ -305,7 +308,7 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
         e = launch_wgrad(k_cins[l], couts, w, s->stream);
         if (e == hipSuccess)
             e = launch_wgrad_reduce(wpart, couts == 8 ? 16 : 32, k_cins[l] == 8 ? 16 : 32, k_chan[l + 1], k_chan[l],
-                                    G + w_off(l), s->stream);
+                                    l == 0 ? k_lo_pairs : 0, G + w_off(l), s->stream);
         if (e == hipSuccess) e = launch_bias_reduce(cpart, k_chan[l + 1], G + b_off(l), s->stream);
         if (l == 0 || e != hipSuccess) break;
         ConvArgs a = {};

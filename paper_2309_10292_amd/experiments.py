@@ -170,7 +170,27 @@ def surrogate(args):
         out["timing"] = dict(ms_surrogate_jump=round(ms_jump, 4), ms_stencil_16_steps_f64=round(ms_stencil, 4),
                              stencil_config=cfg, surrogate_cell_steps_per_s=round(L ** 3 * JUMP / (ms_jump * 1e-3) / 1e9, 2),
                              stencil_cell_steps_per_s=round(L ** 3 * JUMP / (ms_stencil * 1e-3) / 1e9, 2))
-        # controller on held-out trajectories
+        # one jump from stencil states of held-out trajectories: the network
+        # against persistence (no change over 16 steps), both against the
+        # FP64 stencil
+        one = []
+        for b in test_blobs:
+            with gs.Sim(L, L, L, init="none", u0=np.ones((L,) * 3), v0=np.zeros((L,) * 3), F=b["F"], k=b["k"]) as s:
+                s.fill_cube(b["x0"], b["y0"], b["z0"], b["side"])
+                s.step(args.warm)
+                for j in range(4):
+                    u, v, _ = s.current()
+                    u0, v0 = u.clone(), v.clone()
+                    m.predict(u0, v0, b["F"], b["k"], pu, pv)
+                    s.step(JUMP)
+                    u1, v1, _ = s.current()
+                    n2 = 2 * u1.numel()
+                    one.append(dict(net=((gs.sqdiff(pu, u1) + gs.sqdiff(pv, v1)) / n2) ** 0.5,
+                                    persistence=((gs.sqdiff(u0, u1) + gs.sqdiff(v0, v1)) / n2) ** 0.5))
+        out["one_jump_rms"] = dict(net_mean=float(np.mean([x["net"] for x in one])),
+                                   persistence_mean=float(np.mean([x["persistence"] for x in one])), samples=one)
+        # controller on held-out trajectories, with the BF16-storage stencil on
+        # the same trajectory as a second reference point
         runs = []
         for b in test_blobs:
             with gs.Sim(L, L, L, init="none", u0=np.ones((L,) * 3), v0=np.zeros((L,) * 3), F=b["F"], k=b["k"]) as s:
@@ -184,9 +204,17 @@ def surrogate(args):
                     ref.step(args.warm + args.jumps * JUMP)
                     ur, vr, _ = ref.current()
                     rms_end = ((gs.sqdiff(ut, ur) + gs.sqdiff(vt, vr)) / (2 * ur.numel())) ** 0.5
+                    u16 = np.ones((L,) * 3)
+                    with gs.Sim(L, L, L, storage="bf16", init="none", u0=u16, v0=np.zeros((L,) * 3), F=b["F"],
+                                k=b["k"]) as lo:
+                        lo.fill_cube(b["x0"], b["y0"], b["z0"], b["side"])
+                        lo.step(args.warm + args.jumps * JUMP)
+                        ul, vl = lo.read()
+                        uh, vh = ref.read()
+                        rms_bf16 = float(np.sqrt((np.sum((ul - uh) ** 2) + np.sum((vl - vh) ** 2)) / (2 * uh.size)))
                 runs.append(dict(F=b["F"], k=b["k"], checks=r["checks"], fallbacks=r["fallbacks"],
                                  rms_at_checks=[round(x, 6) for x in r["rms"]], rms_end_vs_stencil=rms_end,
-                                 seconds=round(r["seconds"], 4)))
+                                 rms_end_bf16_stencil=rms_bf16, seconds=round(r["seconds"], 4)))
         out["controller"] = dict(tol=args.tol, check_every=4, jumps=args.jumps, runs=runs,
                                  fallback_rate=sum(x["fallbacks"] for x in runs) / max(1, sum(x["checks"] for x in runs)))
     return out

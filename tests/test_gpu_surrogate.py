@@ -60,9 +60,11 @@ def test_forward_matches_oracle(torch):
         # FP32 input path gives the same correction
         pu32, _ = m.predict(ut.float(), vt.float(), F, k)
     params = S.unflatten(bf16_round(p32))
+    # The network reads u and v as BF16 high/low pairs (about 16 significant
+    # bits), so the oracle gets the fields themselves.
     for i in range(n):
-        (eu, ev) = S.forward(params, bf16_round(u[i]), bf16_round(v[i]), float(np.float32(F[i])), float(np.float32(k[i])))
-        du_e, dv_e = eu - bf16_round(u[i]), ev - bf16_round(v[i])
+        (eu, ev) = S.forward(params, u[i], v[i], float(np.float32(F[i])), float(np.float32(k[i])))
+        du_e, dv_e = eu - u[i], ev - v[i]
         du_g, dv_g = pu[i] - u[i], pv[i] - v[i]
         ref = np.concatenate([du_e.ravel(), dv_e.ravel()])
         got = np.concatenate([du_g.ravel(), dv_g.ravel()])
@@ -86,16 +88,13 @@ def test_gradients_match_oracle(torch):
         T = lambda a: torch.from_numpy(a.astype(np.float32)).cuda().contiguous()
         loss, g = m.loss_grad(T(u), T(v), T(ut), T(vt), F, k, want_grad=True)
     params = S.unflatten(bf16_round(p32))
-    # The network sees BF16-rounded (u, v) while the residual adds the FP32
-    # fields; shifting the oracle's targets by the rounding difference makes
-    # its residuals equal to the GPU's.
+    # The GPU gets FP32 fields and reads them as BF16 high/low pairs (about 16
+    # significant bits): the oracle gets the same FP32 values.
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
     samples = []
     for i in range(n):
-        u32, v32 = u[i].astype(np.float32).astype(np.float64), v[i].astype(np.float32).astype(np.float64)
-        ub, vb = bf16_round(u[i]), bf16_round(v[i])
-        samples.append((ub, vb, float(np.float32(F[i])), float(np.float32(k[i])),
-                        ut[i].astype(np.float32).astype(np.float64) - (u32 - ub),
-                        vt[i].astype(np.float32).astype(np.float64) - (v32 - vb)))
+        samples.append((f32(u[i]), f32(v[i]), float(np.float32(F[i])), float(np.float32(k[i])), f32(ut[i]),
+                        f32(vt[i])))
     loss_e, grads = S.loss_and_grads(params, samples)
     print(f"loss gpu {loss:.6e} oracle {loss_e:.6e}")
     assert abs(loss - loss_e) <= 3e-2 * loss_e
