@@ -279,32 +279,53 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     }
 }
 
-// grad[W(co, ci, d)] = sum over workgroups of the partials (fixed order);
-// the first lo_pairs input channels add the partials of their low parts
-// (stored channels cin ..).
+// grad[W(co, ci, d)] = sum over workgroups of the partials; the first
+// lo_pairs input channels add the partials of their low parts (stored
+// channels cin ..). A workgroup handles 64 outputs (input channel fastest, so
+// the loads of a wave are contiguous) with 4 slices each: slice j sums the
+// workgroups b = j, j + 4, ... in order, and the 4 slice sums are added in
+// a fixed order: the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void wgrad_reduce(const float *__restrict__ part, int nblk, int pco, int pci,
                                                     int cout, int cin, int lo_pairs, float *__restrict__ gW)
 {
+    __shared__ double red[4][64];
     const int n = cout * cin * 27;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int d = e % 27, ci = (e / 27) % cin, co = e / (27 * cin);
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(((size_t)b * 27 + d) * pco + co) * pci + ci];
+    const int o = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + o;
+    double s = 0.0;
+    int ci = 0, co = 0, d = 0;
+    if (e < n) {
+        ci = e % cin;
+        co = (e / cin) % cout;
+        d = e / (cin * cout);
+        const size_t stride = (size_t)27 * pco * pci;
+        const float *p = part + ((size_t)d * pco + co) * pci;
+        for (int b = j; b < nblk; b += 4) s += p[(size_t)b * stride + ci];
         if (ci < lo_pairs)
-            for (int b = 0; b < nblk; ++b) s += part[(((size_t)b * 27 + d) * pco + co) * pci + cin + ci];
-        gW[e] = (float)s;
+            for (int b = j; b < nblk; b += 4) s += p[(size_t)b * stride + cin + ci];
     }
+    red[j][o] = s;
+    __syncthreads();
+    if (j == 0 && e < n) gW[((size_t)co * cin + ci) * 27 + d] = (float)((red[0][o] + red[1][o]) + (red[2][o] + red[3][o]));
 }
 
-// Bias gradient: fixed-order fold of the per-workgroup channel sums.
-__global__ __launch_bounds__(64) void colsum_reduce(const float *__restrict__ part, int nblk, int cout,
-                                                    float *__restrict__ gb)
+// Bias gradient: fixed-order fold of the per-workgroup channel sums; 32
+// groups of lanes each sum every 32nd workgroup in order, then lane c adds
+// the 32 group sums of channel c in order.
+__global__ __launch_bounds__(1024) void colsum_reduce(const float *__restrict__ part, int nblk, int cout,
+                                                     float *__restrict__ gb)
 {
-    const int c = threadIdx.x;
-    if (c >= cout) return;
+    __shared__ double red[32][32];
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 32 + c];
-    gb[c] = (float)s;
+    for (int b = g; b < nblk; b += 32) s += part[(size_t)b * 32 + c];
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0 && c < cout) {
+        double t = 0.0;
+        for (int i = 0; i < 32; ++i) t += red[i][c];
+        gb[c] = (float)t;
+    }
 }
 
 // ------------------------------------------------------------------ input, loss, optimiser
@@ -445,14 +466,14 @@ hipError_t launch_wgrad_reduce(const float *part, int pco, int pci, int cout, in
                                hipStream_t st)
 {
     const int n = cout * cin * 27;
-    hipLaunchKernelGGL(wgrad_reduce, dim3(grid_cap(n, 256, 1024)), dim3(256), 0, st, part, wgrad_blocks(), pco, pci,
-                       cout, cin, lo_pairs, gW);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((n + 63) / 64), dim3(256), 0, st, part, wgrad_blocks(), pco, pci, cout, cin,
+                       lo_pairs, gW);
     return hipGetLastError();
 }
 
 hipError_t launch_bias_reduce(const float *bpart, int cout, float *gb, hipStream_t st)
 {
-    hipLaunchKernelGGL(colsum_reduce, dim3(1), dim3(64), 0, st, bpart, wgrad_blocks(), cout, gb);
+    hipLaunchKernelGGL(colsum_reduce, dim3(1), dim3(1024), 0, st, bpart, wgrad_blocks(), cout, gb);
     return hipGetLastError();
 }
 

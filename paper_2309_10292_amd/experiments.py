@@ -145,12 +145,26 @@ def surrogate(args):
             torch.cuda.synchronize()
             t_gen += t1 - t0
             t_train += time.perf_counter() - t1
+            last_data = data
             del data
             curve.append((len(hist), float(np.mean(hist[-20:]))))
             print(json.dumps(dict(chunk=c0 // args.chunk, iters=len(hist), loss=float(np.mean(hist[-20:])),
                                   gen_s=round(t_gen, 1), train_s=round(t_train, 1))), flush=True)
         out["train"] = dict(iters=len(hist), loss_first=float(np.mean(hist[:20])), loss_last=float(np.mean(hist[-50:])),
                             generate_seconds=round(t_gen, 1), train_seconds=round(t_train, 1), curve=curve)
+        # one jump on pairs of the last training chunk: network against
+        # persistence (no change), to tell under- from over-fitting
+        u, v, ut, vt, Fd, kd = last_data
+        pu_, pv_ = torch.empty_like(u[0]), torch.empty_like(v[0])
+        fit = []
+        for i in range(0, u.shape[0], max(1, u.shape[0] // 16)):
+            m.predict(u[i], v[i], float(Fd[i]), float(kd[i]), pu_, pv_)
+            n2 = 2 * u[i].numel()
+            fit.append(dict(net=((gs.sqdiff(pu_, ut[i]) + gs.sqdiff(pv_, vt[i])) / n2) ** 0.5,
+                            persistence=((gs.sqdiff(u[i], ut[i]) + gs.sqdiff(v[i], vt[i])) / n2) ** 0.5))
+        out["train"]["one_jump_rms_last_chunk"] = dict(net_mean=float(np.mean([x["net"] for x in fit])),
+                                                      persistence_mean=float(np.mean([x["persistence"] for x in fit])))
+        del last_data
         params = m.params()
         if args.save:
             np.save(args.save, params)
