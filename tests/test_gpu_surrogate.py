@@ -167,3 +167,89 @@ def test_training_reduces_loss_and_controller(torch):
             u, v = s.read()
         ue, ve = O.run(u0, v0, 64, Du=0.2, Dv=0.1, F=b["F"], k=b["k"], dt=1.0)
         assert np.array_equal(u, ue) and np.array_equal(v, ve)
+
+
+def test_trained_surrogate_gain_l128(torch):
+    """What the trained network gains over the stencil alone, at L=128.
+
+    tests/data/surrogate_l128.npy holds parameters trained on the GPU by
+    `python -m paper_2309_10292_amd.experiments surrogate --epochs 3 --save ...`
+    (2000 stencil trajectories of random cubes at L=128, 22,500 Adam steps).
+    On the experiment's four held-out trajectories (drawn after the training
+    ones from the same seed, never trained on) this measures the one-jump
+    error of the network and of persistence (no change over 16 steps)
+    against the FP64 stencil, the controller's fallbacks with the 1e-3 check
+    every 4th jump, and the time of one jump against 16 stencil steps. It
+    asserts only what the measurement must show regardless of speed: over
+    the four trajectories the network predicts the 16-step change clearly
+    better than persistence (a quiescent trajectory alone can sit below the
+    network's error floor), and the controller's result stays within its
+    tolerance of the plain stencil (bitwise equal when every window falls
+    back). The numbers are printed and, with GS_REPORT_DIR set, written to
+    surrogate_gain_l128.json."""
+    import json
+    import os
+    import time
+    from paper_2309_10292_amd import gs
+    from paper_2309_10292_amd.surrogate import JUMP, Surrogate, run_controlled
+    here = os.path.dirname(os.path.abspath(__file__))
+    params = np.load(os.path.join(here, "data", "surrogate_l128.npy"))
+    assert params.shape == (S.N_PARAMS,) and np.all(np.isfinite(params))
+    L, warm = 128, 64
+    blobs = random_blobs(2004, L, seed=230910292, side_range=(6, 24))[2000:]
+    report = dict(L=L, runs=[])
+
+    def start(b, storage="f64"):
+        s = gs.Sim(L, L, L, storage=storage, init="none", u0=np.ones((L,) * 3), v0=np.zeros((L,) * 3),
+                   F=b["F"], k=b["k"])
+        s.fill_cube(b["x0"], b["y0"], b["z0"], b["side"])
+        s.step(warm)
+        return s
+
+    def rms(a, b, c, d):
+        return ((gs.sqdiff(a, b) + gs.sqdiff(c, d)) / (2 * a.numel())) ** 0.5
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    with Surrogate(L, L, L, max_batch=1, params=params) as m:
+        for b in blobs:
+            with start(b) as s:
+                u, v, _ = s.current()
+                u0, v0 = u.clone(), v.clone()
+                pu, pv = m.predict(u0, v0, b["F"], b["k"])
+                s.step(JUMP)
+                u1, v1, _ = s.current()
+                net, pers = rms(pu, u1, pv, v1), rms(u0, u1, v0, v1)
+                ms_jump = timed(lambda: m.predict(u0, v0, b["F"], b["k"], pu, pv), 10)
+                ms_stencil = timed(lambda: s.step(JUMP), 10)
+            with start(b) as s, start(b) as ref:
+                r = run_controlled(m, s, b["F"], b["k"], jumps=8, check_every=4, tol=1e-3)
+                ref.step(8 * JUMP)
+                uc, vc, stc = s.current()
+                ur, vr, str_ = ref.current()
+                assert stc == str_ == warm + 8 * JUMP
+                end = rms(uc, ur, vc, vr)
+            run = dict(F=b["F"], k=b["k"], one_jump_rms_net=net, one_jump_rms_persistence=pers,
+                       ms_surrogate_jump=ms_jump, ms_stencil_16_steps=ms_stencil, speed_gain=ms_stencil / ms_jump,
+                       checks=r["checks"], fallbacks=r["fallbacks"], rms_at_checks=r["rms"], rms_end_vs_stencil=end)
+            report["runs"].append(run)
+            print(json.dumps(run))
+            if r["fallbacks"] == r["checks"]:
+                assert end == 0.0
+            else:
+                assert end <= 2e-3 * r["checks"], end
+    net_mean = float(np.mean([x["one_jump_rms_net"] for x in report["runs"]]))
+    pers_mean = float(np.mean([x["one_jump_rms_persistence"] for x in report["runs"]]))
+    report.update(one_jump_rms_net_mean=net_mean, one_jump_rms_persistence_mean=pers_mean)
+    print(f"one-jump RMS: network {net_mean:.3e}, persistence {pers_mean:.3e}")
+    assert net_mean < 0.5 * pers_mean, (net_mean, pers_mean)
+    if os.environ.get("GS_REPORT_DIR"):
+        with open(os.path.join(os.environ["GS_REPORT_DIR"], "surrogate_gain_l128.json"), "w") as f:
+            json.dump(report, f, indent=1)
