@@ -38,14 +38,6 @@ __device__ __forceinline__ bf16x8 load8(const u16 *p)
     return __builtin_bit_cast(bf16x8, q);
 }
 
-// Row index (sample * ncell + cell) of the neighbour at offset d of a cell.
-__device__ __forceinline__ size_t nbr_row(const Geo &g, int s, int x, int y, int z, int d)
-{
-    const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
-    const int xn = wrapc(x + dx - 1, g.nx), yn = wrapc(y + dy - 1, g.ny), zn = wrapc(z + dz - 1, g.nz);
-    return (size_t)s * g.ncell + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * zn);
-}
-
 // ------------------------------------------------------------------ convolution
 // MODE_HIDDEN: z = acc + bias, writes z and GELU(z) (32 channels, BF16).
 // MODE_OUT:    pred = residual input + acc + bias for output channels 0, 1.
@@ -194,17 +186,47 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
 
 // ------------------------------------------------------------------ weight gradient
 // dW[d][co][ci] = sum over cells of dz[cell][co] * act[neighbour(cell, d)][ci].
-// A = dz^T (rows co, K = cells), B = act (K = cells, columns ci). Wave w
-// handles offsets d = w, w + 4, ...; each workgroup walks chunks of 32 cells
-// and writes its partial sums (padded 16*MT x 16*NT per offset).
+// A = dz^T (rows co, K = cells), B = act (K = cells, columns ci): both MFMA
+// operands need 8 consecutive cells of one channel per lane, while memory is
+// channels-last, so the operands are transposed on their way into LDS.
+//
+// The workgroups are persistent: each walks work items (a patch of 16 x-cells
+// by 4 y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
+// sums in registers. Per plane z of dz: the act plane z+1 enters an LDS ring
+// of three planes (6 rows x 16 cells per channel, in three copies shifted by
+// x - 1, x, x + 1 so that every B fragment is one aligned 16-byte read), and
+// dz's plane is staged channel-major; wave w then multiplies for the offsets
+// d = w, w + 4, ... (two K chunks of 32 cells each). Channel rows are padded
+// so that the 16 lanes of a fragment read hit distinct banks. The bias
+// gradient (the sum of dz over cells) is accumulated while dz is staged. Each
+// workgroup writes its partial sums (padded 16*MT x 16*NT per offset, and 32
+// bias sums) once.
+constexpr int WG_ZC = 16;
+
 template <int CIN, int COUTS, int MT, int NT>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
 {
-    constexpr int ND = 7; // ceil(27 / 4)
+    constexpr int ND = 7;                   // ceil(27 / 4) offsets per wave
+    constexpr int NCI = 16 * NT, NCO = 16 * MT;
+    constexpr int AS = 6 * 16 + 8;          // u16 per channel of one act copy (6 rows x 16 cells, padded)
+    constexpr int DS = 64 + 8;              // u16 per channel of the dz plane (4 rows x 16 cells, padded)
+    constexpr int NCG = CIN / 8, NCGZ = COUTS / 8;
+    constexpr int T_ACT = 3 * 6 * 4 * NCG;  // staging tasks of one act plane: copy x row x 4-cell group x 8 channels
+    constexpr int T_DZ = 4 * 4 * NCGZ;      // staging tasks of one dz plane
+    static_assert(T_DZ <= 256, "one dz staging task per lane");
+    __shared__ __align__(16) u16 act_l[9 * NCI * AS]; // [ring slot][copy][channel][row][cell]
+    __shared__ __align__(16) u16 dz_l[NCO * DS];      // [channel][row * 16 + cell]
+    __shared__ float bsum_l[T_DZ][8];
     const Geo g = a.geo;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, quad = lane >> 4;
+
+    // Channel rows past CIN / COUTS stay zero.
+    for (int e = tid; e < 9 * NCI * AS; e += 256)
+        if ((e / AS) % NCI >= CIN) act_l[e] = 0;
+    for (int e = tid; e < NCO * DS; e += 256)
+        if (e / DS >= COUTS) dz_l[e] = 0;
+
     f32x4 acc[ND][MT][NT];
 #pragma unroll
     for (int i = 0; i < ND; ++i)
@@ -212,55 +234,137 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[i][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum[MT];
+    float bs[8];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) bsum[m] = 0.f;
-    const size_t rows = (size_t)a.nsamp * g.ncell;
-    const size_t n_kc = rows / 32;
-    for (size_t kc = blockIdx.x; kc < n_kc; kc += gridDim.x) {
-        const size_t r0 = kc * 32 + 8 * quad; // this lane's 8 cells: r0 .. r0 + 7 (one x-row)
-        const int s = (int)(r0 / g.ncell);
-        const int c0 = (int)(r0 % g.ncell);
-        const int x0 = c0 % g.nx, y = (c0 / g.nx) % g.ny, z = c0 / (g.nx * g.ny);
-        bf16x8 av[MT];
+    for (int c = 0; c < 8; ++c) bs[c] = 0.f;
+
+    // Four cells (8 channels each, one uint4 per cell) -> 8 channels x 4 cells
+    // (one uint2 per channel).
+    auto transpose_store = [&](const uint4 (&q)[4], u16 *dst, int stride) {
+        const uint32_t *w0 = reinterpret_cast<const uint32_t *>(&q[0]);
+        const uint32_t *w1 = reinterpret_cast<const uint32_t *>(&q[1]);
+        const uint32_t *w2 = reinterpret_cast<const uint32_t *>(&q[2]);
+        const uint32_t *w3 = reinterpret_cast<const uint32_t *>(&q[3]);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int co = 16 * m + col;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const u16 b = co < COUTS ? a.dz[(r0 + j) * COUTS + co] : (u16)0;
-                av[m][j] = __builtin_bit_cast(__bf16, b);
-                bsum[m] += bf2f(b); // bias gradient: the same sum over cells without the input
+        for (int c = 0; c < 8; ++c) {
+            const int wi = c >> 1;
+            uint2 o;
+            if (c & 1) {
+                o.x = (w0[wi] >> 16) | (w1[wi] & 0xffff0000u);
+                o.y = (w2[wi] >> 16) | (w3[wi] & 0xffff0000u);
+            } else {
+                o.x = (w0[wi] & 0xffffu) | (w1[wi] << 16);
+                o.y = (w2[wi] & 0xffffu) | (w3[wi] << 16);
             }
+            *reinterpret_cast<uint2 *>(dst + c * stride) = o;
         }
+    };
+
+    const int ntx = g.nx / 16, nty = (g.ny + 3) / 4, ntz = (g.nz + WG_ZC - 1) / WG_ZC;
+    const int nitems = ntx * nty * ntz * a.nsamp;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int r = it;
+        const int tx = r % ntx;
+        r /= ntx;
+        const int ty = r % nty;
+        r /= nty;
+        const int tz = r % ntz;
+        const int smp = r / ntz;
+        const int x0 = tx * 16, y0 = ty * 4, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
+        const size_t sbase = (size_t)smp * g.ncell;
+
+        // act plane p (z0 - 1 <= p <= ze) into ring slot (p - z0 + 1) mod 3
+        auto stage_act = [&](int p) {
+            const int slot = (p - z0 + 1) % 3;
+            const int zp = wrapc(p, g.nz);
+            for (int t = tid; t < T_ACT; t += 256) {
+                const int cg = t % NCG;
+                int rest = t / NCG;
+                const int g4 = rest % 4;
+                rest /= 4;
+                const int rr = rest % 6;
+                const int sc = rest / 6;
+                const int y = wrapc(y0 + rr - 1, g.ny);
+                const size_t rowbase = sbase + ((size_t)zp * g.ny + y) * g.nx;
+                uint4 q[4];
 #pragma unroll
-        for (int i = 0; i < ND; ++i) {
-            const int d = wave + 4 * i;
-            if (d >= 27) break;
+                for (int k = 0; k < 4; ++k) {
+                    const int x = wrapc(x0 + 4 * g4 + k + sc - 1, g.nx);
+                    q[k] = *reinterpret_cast<const uint4 *>(a.act + (rowbase + x) * CIN + 8 * cg);
+                }
+                transpose_store(q, act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 4 * g4, AS);
+            }
+        };
+        // dz plane z (rows past ny contribute zero)
+        auto stage_dz = [&](int z) {
+            if (tid < T_DZ) {
+                const int cg = tid % NCGZ;
+                const int g4 = (tid / NCGZ) % 4;
+                const int rr = tid / (4 * NCGZ);
+                const int y = y0 + rr;
+                uint4 q[4];
+                if (y < g.ny) {
+                    const size_t base = sbase + ((size_t)z * g.ny + y) * g.nx + x0 + 4 * g4;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const int ci = 16 * n + col;
-                bf16x8 bv;
+                    for (int k = 0; k < 4; ++k) q[k] = *reinterpret_cast<const uint4 *>(a.dz + (base + k) * COUTS + 8 * cg);
+                } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const u16 b = ci < CIN ? a.act[nbr_row(g, s, x0 + j, y, z, d) * CIN + ci] : (u16)0;
-                    bv[j] = __builtin_bit_cast(__bf16, b);
+                    for (int k = 0; k < 4; ++k) q[k] = uint4{0u, 0u, 0u, 0u};
                 }
 #pragma unroll
-                for (int m = 0; m < MT; ++m)
-                    acc[i][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv, acc[i][m][n], 0, 0, 0);
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(&q[k]);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
+                }
+                transpose_store(q, dz_l + (8 * cg) * DS + rr * 16 + 4 * g4, DS);
             }
+        };
+
+        stage_act(z0 - 1);
+        stage_act(z0);
+        for (int z = z0; z < ze; ++z) {
+            stage_act(z + 1);
+            stage_dz(z);
+            __syncthreads();
+            bf16x8 af[2][MT];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) af[c][m] = load8(dz_l + (16 * m + col) * DS + 32 * c + 8 * quad);
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+                const int d = wave + 4 * i;
+                if (d >= 27) break;
+                const int dzo = d / 9 - 1, dyo = (d / 3) % 3 - 1, dxo = d % 3 - 1;
+                const int slot = (z - z0 + 1 + dzo) % 3;
+                const u16 *bbase = act_l + (slot * 3 + dxo + 1) * NCI * AS + 8 * (quad & 1);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int row = 2 * c + (quad >> 1) + dyo + 1;
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) {
+                        const bf16x8 bv = load8(bbase + (16 * n + col) * AS + row * 16);
+#pragma unroll
+                        for (int m = 0; m < MT; ++m)
+                            acc[i][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[c][m], bv, acc[i][m][n], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads(); // the ring slot and the dz plane are rewritten next
         }
     }
-    // Bias partials: lanes col, col + 16, col + 32, col + 48 hold the four
-    // 8-cell groups of channel 16 m + col; every wave loaded the same dz, so
-    // wave 0 writes them.
+
+    // Bias partials: lane t < T_DZ summed channels 8 (t % NCGZ) + c; fold the
+    // lanes of each channel in lane order.
+    if (tid < T_DZ)
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        float t = bsum[m];
-        t += __shfl_xor(t, 16, 64);
-        t += __shfl_xor(t, 32, 64);
-        if (wave == 0 && quad == 0) a.bpart[(size_t)blockIdx.x * 32 + 16 * m + col] = t;
+        for (int c = 0; c < 8; ++c) bsum_l[tid][c] = bs[c];
+    __syncthreads();
+    if (tid < COUTS) {
+        float t = 0.f;
+        for (int l = tid / 8; l < T_DZ; l += NCGZ) t += bsum_l[l][tid % 8];
+        a.bpart[(size_t)blockIdx.x * 32 + tid] = t;
     }
     // acc[i][m][n][j]: offset d, co = 16 m + 4 quad + j, ci = 16 n + col.
     constexpr int PCO = 16 * MT, PCI = 16 * NT;

@@ -260,6 +260,7 @@ def main(argv=None):
     s = json.dumps(res)
     print(s)
     if a.out:
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         with open(a.out, "w") as f:
             f.write(s + "\n")
 
