@@ -221,23 +221,26 @@ gs_status check(gs_sim *s)
 }
 
 // Library choice of the launch configuration before any tuning (from the
-// MI355X sweep at 512^3): large FP64/FP32 grids use the temporally blocked
-// kernel with three fused steps and 128-plane chunks; 16-bit storage is
-// arithmetic-bound and gains nothing from fusing, so it keeps the
-// single-step kernel; small grids keep the single-step kernel with short
-// chunks so that enough workgroups exist.
+// MI355X autotuner sweeps at 512^3 and 1024^3): large grids use the
+// temporally blocked kernel: FP64 with three fused steps (64 x 22 tiles, 512
+// lanes, 128-plane chunks), FP32 with two (the compensated Laplacian makes
+// deeper fusion arithmetic-bound; 64-plane chunks) and FP16 with one step in
+// 768-lane workgroups; BF16 keeps the single-step kernel. Small grids keep
+// the single-step kernel with short chunks so that enough workgroups exist.
 bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
 {
-    if (large_grid(p) && (p.storage == GS_F64 || p.storage == GS_F32)) return gs::num_tiles() + 2;
+    if (!large_grid(p)) return 1;
+    if (p.storage == GS_F64 || p.storage == GS_F32) return gs::num_tiles() + 2;
+    if (p.storage == GS_F16) return gs::num_tiles() + 4;
     return 1;
 }
 
 int default_tblock(const gs_params &p, int tile)
 {
     if (tile <= gs::num_tiles()) return 1;
-    const int T = (p.storage == GS_F64 || p.storage == GS_F32) ? 3 : 1;
+    const int T = p.storage == GS_F64 ? 3 : p.storage == GS_F32 ? 2 : 1;
     const int mt = tile_max_tblock(tile, p.storage);
     return T < mt ? T : mt;
 }
@@ -245,7 +248,7 @@ int default_tblock(const gs_params &p, int tile)
 int default_zc(const gs_params &p, int tile)
 {
     int z = 16;
-    if (large_grid(p)) z = tile > gs::num_tiles() ? 128 : 32;
+    if (large_grid(p)) z = tile <= gs::num_tiles() ? 32 : (p.storage == GS_F64 ? 128 : 64);
     return p.nz < z ? p.nz : z;
 }
 

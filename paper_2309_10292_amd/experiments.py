@@ -62,7 +62,7 @@ def precision(args):
             d = s.diagnostics(allow_nonfinite=True)
         bpc = {"f64": 32, "f32": 16, "bf16": 8, "f16": 8}[storage]
         rec = dict(gcells=round(L ** 3 * n / (ms * 1e-3) / 1e9, 2), ms_per_step=round(ms / n, 4), launch=cfg,
-                   single_step_equivalent_gbs=round(bpc * L ** 3 * n / (ms * 1e-3) / 1e9, 1),
+                   algorithmic_gbs=round(bpc * L ** 3 * n / (ms * 1e-3) / 1e9, 1),
                    sum_u=d["sum_u"], sum_v=d["sum_v"], nonfinite=d["nonfinite"])
         out["storage"][storage] = rec
         print(json.dumps({storage: rec}), flush=True)
