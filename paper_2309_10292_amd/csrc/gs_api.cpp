@@ -224,15 +224,18 @@ gs_status check(gs_sim *s)
 // MI355X autotuner sweeps at 512^3 and 1024^3): large grids use the
 // temporally blocked kernel: FP64 with three fused steps (64 x 22 tiles, 512
 // lanes, 128-plane chunks), FP32 with two (the compensated Laplacian makes
-// deeper fusion arithmetic-bound; 64-plane chunks) and FP16 with one step in
-// 768-lane workgroups; BF16 keeps the single-step kernel. Small grids keep
-// the single-step kernel with short chunks so that enough workgroups exist.
+// deeper fusion arithmetic-bound): 512 lanes and 64-plane chunks without
+// noise, 1024 lanes and 32-plane chunks with noise (whose Philox work wants
+// more waves per SIMD); FP16 with one step in 768-lane workgroups; BF16 keeps
+// the single-step kernel. Small grids keep the single-step kernel with short
+// chunks so that enough workgroups exist.
 bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
 {
     if (!large_grid(p)) return 1;
-    if (p.storage == GS_F64 || p.storage == GS_F32) return gs::num_tiles() + 2;
+    if (p.storage == GS_F64) return gs::num_tiles() + 2;
+    if (p.storage == GS_F32) return gs::num_tiles() + (p.noise != 0.0 ? 5 : 2);
     if (p.storage == GS_F16) return gs::num_tiles() + 4;
     return 1;
 }
@@ -248,7 +251,8 @@ int default_tblock(const gs_params &p, int tile)
 int default_zc(const gs_params &p, int tile)
 {
     int z = 16;
-    if (large_grid(p)) z = tile <= gs::num_tiles() ? 32 : (p.storage == GS_F64 ? 128 : 64);
+    if (large_grid(p))
+        z = tile <= gs::num_tiles() ? 32 : p.storage == GS_F64 ? 128 : (p.storage == GS_F32 && p.noise != 0.0) ? 32 : 64;
     return p.nz < z ? p.nz : z;
 }
 
