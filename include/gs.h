@@ -63,7 +63,8 @@ typedef struct gs_params {
     double Du, Dv;        /* diffusion rates, finite, >= 0 */
     double F, k;          /* feed and kill rates, finite */
     double dt;            /* time step, finite */
-    double noise;         /* magnitude n of the noise term n r on U; finite, >= 0; 0 disables it */
+    double noise;         /* magnitude n of the noise term n r on U; finite, 0 (disables it) or in
+                             [2^-990, inf) (GS_ERR_UNSUPPORTED below) */
     uint64_t seed;        /* Philox4x32-10 key for r */
     uint64_t step0;       /* global index of the initial state's step (resume) */
     int32_t init_mode;    /* gs_init_mode */

@@ -72,6 +72,10 @@ gs_status validate(const gs_params *p)
         if (!std::isfinite(c[i])) return fail(GS_ERR_INVALID_ARG, "%s is not finite", nm[i]);
     if (p->Du < 0 || p->Dv < 0) return fail(GS_ERR_INVALID_ARG, "diffusion rates must be >= 0");
     if (p->noise < 0) return fail(GS_ERR_INVALID_ARG, "noise must be >= 0");
+    // The FP64 kernels scale the noise by 2^-32 exactly; below this bound the
+    // scaled value would be subnormal.
+    if (p->noise != 0 && p->noise < 0x1p-990)
+        return fail(GS_ERR_UNSUPPORTED, "noise %g below 2^-990 is not supported", p->noise);
     if (p->init_mode != GS_INIT_NONE && p->init_mode != GS_INIT_CUBE)
         return fail(GS_ERR_INVALID_ARG, "unknown init_mode %d", p->init_mode);
     if (p->init_mode == GS_INIT_CUBE) {
@@ -269,6 +273,8 @@ gs::StepArgs make_args(const gs_sim *s)
     a.FK = s->p.F + s->p.k;
     a.dt = s->p.dt;
     a.noise = s->p.noise;
+    a.noise_s = std::ldexp(a.noise, -31);
+    a.noise_h = std::ldexp(a.noise, -32);
     a.Du_f = (float)a.Du;
     a.Dv_f = (float)a.Dv;
     a.F_f = (float)a.F;

@@ -112,6 +112,8 @@ gs::StepArgs shared_coef(const gs_batch *b)
     a.Dv = b->base.Dv;
     a.dt = b->base.dt;
     a.noise = b->base.noise;
+    a.noise_s = std::ldexp(a.noise, -31);
+    a.noise_h = std::ldexp(a.noise, -32);
     a.Du_f = (float)a.Du;
     a.Dv_f = (float)a.Dv;
     a.dt_f = (float)a.dt;

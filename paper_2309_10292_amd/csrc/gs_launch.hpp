@@ -13,6 +13,7 @@ struct StepArgs {
     int zc;              // planes per z-chunk
     int ntx, nty;        // tiles per row / column (set by the launcher)
     double Du, Dv, F, FK, dt, noise;   // FK = F + k, rounded once
+    double noise_s, noise_h;           // noise 2^-31 and noise 2^-32 (exact: |noise| >= 2^-990 or 0)
     float Du_f, Dv_f, F_f, FK_f, dt_f, noise_f;
     uint64_t seed;
     uint64_t t;          // global index of the step being taken (noise key)

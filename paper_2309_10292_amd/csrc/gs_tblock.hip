@@ -89,15 +89,21 @@ template <bool F> struct Full {
 __host__ __device__ constexpr int slot3(int p) { return ((p % 3) + 3) % 3; }
 
 // UNIT_DT: dt is exactly 1, so the products du dt and dv dt equal du and dv
-// (bitwise) and are skipped.
+// (bitwise) and are skipped. In FP64, nr is the noise term n r itself; in
+// FP32 it is r.
 template <typename C, bool UNIT_DT>
-__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, bool noisy, C r, C &uo, C &vo)
+__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, bool noisy, C nr, C &uo, C &vo)
 {
     const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
     const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
     const C uvv = uc * (vc * vc);
     C du = (Du * lu - uvv) + F * ((C)1 - uc);
-    if (noisy) du = du + Coef<C>::noise(a) * r;
+    if (noisy) {
+        if constexpr (sizeof(C) == 8)
+            du = du + nr;
+        else
+            du = du + Coef<C>::noise(a) * nr;
+    }
     const C dv = (Dv * lv + uvv) - FK * vc;
     if constexpr (UNIT_DT) {
         uo = uc + du;
@@ -241,14 +247,17 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                     yp[f][e] = lds_at(f, k - 1, row + 1, 4 * gxs + e);
                 }
             }
-            C r[4] = {(C)0, (C)0, (C)0, (C)0};
+            C r[4] = {(C)0, (C)0, (C)0, (C)0}; // FP64: the noise term n r; FP32: r
             if constexpr (NOISE) {
                 const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
                 const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
+                    // FP64: n r with r = (w + 1/2) 2^-31 is the exact real
+                    // (n 2^-31) w + n 2^-32, so one fused operation rounds it
+                    // once, as the product n r does.
                     if constexpr (sizeof(C) == 8)
-                        r[e] = noise_word_f64(w.w[e]);
+                        r[e] = __builtin_fma(a.noise_s, (double)(int32_t)w.w[e], a.noise_h);
                     else
                         r[e] = noise_word_f32(w.w[e]);
                 }

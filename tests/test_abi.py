@@ -154,3 +154,14 @@ def test_batch_max_tblock():
             mb = L.gs_batch_max_tblock(t, s)
             assert 0 <= mb <= gs.max_tblock(t, s) <= 4
     assert gs.max_tblock(6, "f64") == 4 and gs.max_tblock(6, "f64", batch=True) == 4
+
+
+def test_noise_below_bound_rejected():
+    """Noise amplitudes in (0, 2^-990) would make the kernels' exactly scaled
+    noise subnormal; gs_init rejects them before any HIP call."""
+    import math
+    L = gs.load()
+    assert gs.workspace_bytes(gs.make_params(16, 16, 16, noise=math.ldexp(1.0, -990))) > 0
+    p = gs.make_params(16, 16, 16, noise=math.ldexp(1.0, -1000))
+    assert gs.workspace_bytes(p) == 0
+    assert L.gs_init(ctypes.byref(p), None, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == gs.GS_ERR_UNSUPPORTED
