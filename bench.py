@@ -111,7 +111,14 @@ def cpu_baseline(L, p, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return dict(value=round(L ** 3 * done / el / 1e9, 4), unit="Gcell-updates/s", cores=threads, kind="oracle",
+                cpu_model=model,
                 sample=f"{done} whole-grid FP64 steps of the {L}^3 noisy workload, {el:.1f} s on {threads} threads")
 
 

@@ -191,7 +191,15 @@ gs_status gs_get_config(gs_sim *s, int32_t *tile, int32_t *tblock, int32_t *zchu
  * step index are unchanged. Selects the fastest (time per step) for later
  * gs_step / gs_step_graph calls. If `table` is non-NULL the first `capacity`
  * measurements are written there; *n_entries (if non-NULL) receives the
- * number of candidates measured. */
+ * number of candidates measured.
+ * Tuning cache: when the environment variable GS_TUNE_CACHE names a file, the
+ * choice is recorded there (one JSON object per line, keyed by storage type,
+ * nx, ny, nz and whether noise is on; an existing entry for the key is
+ * replaced), and gs_init uses a recorded choice for the same key when
+ * gs_params leaves tile, tblock and zchunk all 0. If the file cannot be
+ * written, gs_tune returns GS_ERR_INVALID_ARG and the handle keeps the tuned
+ * configuration. gs_batch_tune and gs_batch_init do the same per grid class
+ * ("kind":"batch" entries). */
 gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacity, int32_t *n_entries);
 
 /* Same result as gs_step(s, n_steps), enqueued as one HIP graph replay. The

@@ -390,6 +390,17 @@ gs_status gs_init(const gs_params *p, void *u0, void *v0, void *u1, void *v1, vo
     s->tile = p->tile ? p->tile : default_tile(*p);
     s->zc = p->zchunk ? (p->zchunk < p->nz ? p->zchunk : p->nz) : default_zc(*p, s->tile);
     s->tblock = p->tblock ? p->tblock : default_tblock(*p, s->tile);
+    if (p->tile == 0 && p->tblock == 0 && p->zchunk == 0) {
+        // a configuration recorded by gs_tune for this grid class, if any
+        TuneVal v;
+        const TuneKey key = {TUNE_SINGLE, p->storage, p->nx, p->ny, p->nz, p->noise != 0.0};
+        if (tune_cache_lookup(key, &v) && v.tile >= 1 && v.tile <= total_tiles() && v.tblock >= 1 &&
+            v.tblock <= tile_max_tblock(v.tile, p->storage) && v.zchunk >= 1) {
+            s->tile = v.tile;
+            s->tblock = v.tblock;
+            s->zc = v.zchunk < p->nz ? v.zchunk : p->nz;
+        }
+    }
     s->n = (size_t)p->nx * p->ny * p->nz;
     s->graph = GraphCache();
     s->capture_stream = nullptr;
@@ -586,6 +597,9 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
     s->tblock = bT;
     s->zc = bz;
     if (n_entries) *n_entries = count;
+    const TuneKey key = {TUNE_SINGLE, s->p.storage, s->p.nx, s->p.ny, s->p.nz, s->p.noise != 0.0};
+    if (!tune_cache_store(key, TuneVal{bt, bT, bz, best}))
+        return fail(GS_ERR_INVALID_ARG, "tuned, but the table %s could not be written", tune_cache_path());
     return GS_OK;
 }
 

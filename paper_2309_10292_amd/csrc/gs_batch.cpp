@@ -372,6 +372,18 @@ gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx
         s.T = T;
         const int zc = base->zchunk ? base->zchunk : 32;
         s.zc = std::min(zc, s.nz);
+        if (base->tile == 0 && base->tblock == 0 && base->zchunk == 0) {
+            // a configuration recorded by gs_batch_tune for this grid class, if any
+            TuneVal v;
+            const TuneKey key = {TUNE_BATCH, base->storage, s.nx, s.ny, s.nz, base->noise != 0.0};
+            if (tune_cache_lookup(key, &v) && v.tile > gs::num_tiles() &&
+                v.tile <= gs::num_tiles() + gs::num_tb_shapes() && v.tblock >= 1 &&
+                v.tblock <= gs::tb_batch_max_T(v.tile - gs::num_tiles(), base->storage) && v.zchunk >= k_min_batch_zc) {
+                s.shape = v.tile - gs::num_tiles();
+                s.T = v.tblock;
+                s.zc = std::min(v.zchunk, s.nz);
+            }
+        }
         b->sims.push_back(s);
         if (base->init_mode == GS_INIT_CUBE) {
             e = gs::launch_init_cube(base->storage, s.buf[0][0], s.buf[0][1], s.nx, s.ny, s.nz, base->cube_side,
@@ -524,6 +536,7 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
     }
     static const int zcs[] = {16, 32, 64, 128};
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool cache_ok = true;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) {
@@ -602,6 +615,10 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
             b->sims[i].zc = bz;
             desc[i].zc = bz;
         }
+        if (e == hipSuccess &&
+            !tune_cache_store(TuneKey{TUNE_BATCH, b->base.storage, k.nx, k.ny, k.nz, b->base.noise != 0.0},
+                              TuneVal{bs + gs::num_tiles(), bT, bz, best}))
+            cache_ok = false;
         if ((int32_t)c < capacity) {
             gs_batch_tune_entry &t = table[c];
             t.nx = k.nx;
@@ -622,7 +639,10 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
     if (n_entries) *n_entries = (int32_t)classes.size();
     (void)count;
     b->dirty = true;
-    return rebuild(b);
+    st = rebuild(b);
+    if (st == GS_OK && !cache_ok)
+        return fail(GS_ERR_INVALID_ARG, "tuned, but the table %s could not be written", tune_cache_path());
+    return st;
 }
 
 gs_status gs_batch_current(gs_batch *b, int32_t sim, void **u_dev, void **v_dev, uint64_t *step)

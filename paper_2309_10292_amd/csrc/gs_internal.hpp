@@ -24,4 +24,20 @@ gs_status diagnostics(int32_t storage, const void *u, const void *v, size_t n, v
 // Byte offset of the graph-replay step counter inside a workspace.
 size_t counter_offset();
 
+// Autotuner cache (file named by GS_TUNE_CACHE; see gs_tunecache.cpp).
+enum { TUNE_SINGLE = 0, TUNE_BATCH = 1 };
+struct TuneKey {
+    int kind;          // TUNE_SINGLE or TUNE_BATCH
+    int storage;
+    int nx, ny, nz;
+    int noisy;         // noise != 0
+};
+struct TuneVal {
+    int tile, tblock, zchunk;
+    double ms_per_step;
+};
+const char *tune_cache_path();
+bool tune_cache_lookup(const TuneKey &key, TuneVal *val);
+bool tune_cache_store(const TuneKey &key, const TuneVal &val); // false if the table could not be written
+
 } // namespace gsapi

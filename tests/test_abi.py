@@ -165,3 +165,40 @@ def test_noise_below_bound_rejected():
     p = gs.make_params(16, 16, 16, noise=math.ldexp(1.0, -1000))
     assert gs.workspace_bytes(p) == 0
     assert L.gs_init(ctypes.byref(p), None, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == gs.GS_ERR_UNSUPPORTED
+
+
+def test_tune_cache_lookup(tmp_path, monkeypatch):
+    """gs_init takes a configuration recorded in the GS_TUNE_CACHE table for
+    the same (storage, nx, ny, nz, noise on/off) when gs_params leaves the
+    launch configuration to the library, and ignores entries for other keys,
+    entries the library cannot run and malformed lines. (No HIP call: the
+    state is not initialised and the handle is not destroyed.)"""
+    L = gs.load()
+    cache = tmp_path / "tune.jsonl"
+    line = ('{{"kind":"{kind}","storage":{st},"nx":{nx},"ny":32,"nz":32,"noise":{nz},'
+            '"tile":{t},"tblock":{T},"zchunk":{zc},"ms_per_step":0.1}}')
+    cache.write_text("\n".join([
+        "not json at all",
+        line.format(kind="single", st=0, nx=64, nz=0, t=7, T=2, zc=8),    # used for the f64 64x32x32 grid
+        line.format(kind="single", st=0, nx=64, nz=1, t=6, T=3, zc=16),   # same grid with noise
+        line.format(kind="batch", st=0, nx=64, nz=0, t=5, T=1, zc=16),    # another kind
+        line.format(kind="single", st=0, nx=32, nz=0, t=9, T=4, zc=8),    # tile 9 fuses at most 1 step in FP64
+    ]) + "\n")
+    monkeypatch.setenv("GS_TUNE_CACHE", str(cache))
+    buf = ctypes.create_string_buffer(4096 + 256)
+    base = (ctypes.addressof(buf) + 255) // 256 * 256
+    ptrs = [ctypes.c_void_p(base + 256 * i) for i in range(5)]
+
+    def config(nx, noise=0.0, tile=0):
+        p = gs.make_params(nx, 32, 32, noise=noise, init="none", tile=tile)
+        h = ctypes.c_void_p()
+        assert L.gs_init(ctypes.byref(p), *ptrs[:4], ptrs[4], None, ctypes.byref(h)) == gs.GS_OK
+        t, T, zc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert L.gs_get_config(h, ctypes.byref(t), ctypes.byref(T), ctypes.byref(zc)) == gs.GS_OK
+        return t.value, T.value, zc.value
+
+    assert config(64) == (7, 2, 8)
+    assert config(64, noise=1e-7) == (6, 3, 16)
+    default = config(48)                      # no entry
+    assert config(32) == default              # unrunnable entry ignored
+    assert config(64, tile=1)[0] == 1         # an explicit choice wins over the table

@@ -368,3 +368,41 @@ def test_tune_leaves_state_and_picks_valid_config(torch):
     u0, v0 = O.init_cube(shape=shape, side=20)
     ue, ve = O.run(u0, v0, 8, **p)
     assert np.array_equal(u, ue) and np.array_equal(v, ve)
+
+
+def test_tune_cache_roundtrip(torch, tmp_path, monkeypatch):
+    """With GS_TUNE_CACHE set, gs_tune records its choice and a new handle for
+    the same grid class starts with it; gs_batch_tune does the same per grid
+    class of a batch. The recorded configurations give the oracle's result."""
+    import json
+    from paper_2309_10292_amd import gs
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("GS_TUNE_CACHE", str(cache))
+    shape = (32, 40, 64)
+    p = dict(P0, noise=1e-3, seed=8)
+    with _sim(shape, cube_side=10, **p) as s:
+        cfg, _ = s.tune(reps=1)
+    entries = [json.loads(l) for l in cache.read_text().splitlines()]
+    assert len(entries) == 1
+    e = entries[0]
+    assert (e["kind"], e["storage"], e["nx"], e["ny"], e["nz"], e["noise"]) == ("single", 0, 64, 40, 32, 1)
+    assert (e["tile"], e["tblock"], e["zchunk"]) == (cfg["tile"], cfg["tblock"], cfg["zchunk"])
+    with _sim(shape, cube_side=10, **p) as s:
+        assert s.config() == cfg
+        s.step(7)
+        u, v = s.read()
+    u0, v0 = O.init_cube(shape=shape, side=10)
+    ue, ve = O.run(u0, v0, 7, **p)
+    assert np.array_equal(u, ue) and np.array_equal(v, ve)
+    # batched: one entry per grid class, used by a new batch
+    sims = [dict(L=32, F=0.02, k=0.048), dict(L=48, F=0.03, k=0.055), dict(L=32, F=0.045, k=0.06)]
+    with gs.Batch(sims, cube_side=8, Du=0.2, Dv=0.1, dt=1.0) as b:
+        table = b.tune(reps=1)
+        chosen = {e["nx"]: (e["tile"], e["tblock"], e["zchunk"]) for e in table}
+    entries = [json.loads(l) for l in cache.read_text().splitlines()]
+    batch = {e["nx"]: (e["tile"], e["tblock"], e["zchunk"]) for e in entries if e["kind"] == "batch"}
+    assert batch == chosen and len(entries) == 3
+    with gs.Batch(sims, cube_side=8, Du=0.2, Dv=0.1, dt=1.0) as b:
+        for i, sm in enumerate(sims):
+            c = b.config(i)
+            assert (c["tile"], c["tblock"], c["zchunk"]) == chosen[sm["L"]]
