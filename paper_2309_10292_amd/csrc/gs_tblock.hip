@@ -20,9 +20,10 @@
 //     from level k-1's current plane staged in LDS;
 //   - level T's plane is stored if it lies in the workgroup's chunk;
 //   - each level's newest plane is staged in LDS for the next iteration.
-// Cells are evaluated by the same operation sequence as the single-step
-// kernel, so results are bitwise independent of T and of the tile. The noise
-// of level k uses step index t + k - 1.
+// Every cell-update rounds exactly as the single-step kernel's (the same
+// operation sequence; in FP64 the noise term n r is one fused operation on the
+// same exact real), so results are bitwise independent of T and of the tile.
+// The noise of level k uses step index t + k - 1.
 #include "gs_device.hpp"
 #include "gs_launch.hpp"
 
@@ -391,9 +392,16 @@ __global__ __launch_bounds__(NT) void stencil_tb_batch(BatchArgs b)
         const S *v = (const S *)d.buf[b.parity][1];
         S *un = (S *)d.buf[b.parity ^ 1][0];
         S *vn = (S *)d.buf[b.parity ^ 1][1];
-        tb_tile<S, TXG, TY, T, NT, NOISE, true, false>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0,
-                                                       min(z0 + d.zc, d.nz), t0,
-                                          lds);
+        const int ze = min(z0 + d.zc, d.nz);
+        if constexpr (sizeof(S) == 8) {
+            if (a.dt == 1.0) {
+                tb_tile<S, TXG, TY, T, NT, NOISE, true, true>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, ze,
+                                                              t0, lds);
+                continue;
+            }
+        }
+        tb_tile<S, TXG, TY, T, NT, NOISE, true, false>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, ze, t0,
+                                                       lds);
     }
 }
 
