@@ -123,7 +123,7 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is None:
         if not os.path.exists(path):
-            raise RuntimeError(f"libgs.so not found at {path}: run __graft_entry__.build() "
+            raise RuntimeError(f"libgs.so not found at {path}: build it with python paper_2309_10292_amd/build.py "
                                "(the HIP library is required; there is no fallback)")
         L = ctypes.CDLL(path)
         for name, res, args in SIGNATURES:
