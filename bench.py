@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -137,7 +138,9 @@ def main():
     L = a.L
     p = {k: wl[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
 
-    def measure(storage, steps, warmup, main=False):
+    want_err = a.storage == "f64" and a.variants != "none"
+
+    def measure(storage, steps, warmup, main=False, fields=False):
         kw = dict(tile=a.tile, tblock=a.tblock, zchunk=a.zchunk) if main else {}
         with gs.Sim(L, L, L, storage=storage, cube_side=wl["cube_side"], **kw, **p) as s:
             if main and a.tune:
@@ -145,9 +148,10 @@ def main():
             cfg = s.config()
             ms, per_launch, launches = time_steps(torch, s, steps, warmup)
             d = s.diagnostics(allow_nonfinite=True)
-        return ms, per_launch, launches, cfg, d
+            uv = s.read() if fields else None  # FP64 host copies of the final state
+        return ms, per_launch, launches, cfg, d, uv
 
-    ms, per_launch, launches, cfg, diag = measure(a.storage, a.steps, a.warmup, main=True)
+    ms, per_launch, launches, cfg, diag, ref = measure(a.storage, a.steps, a.warmup, main=True, fields=want_err)
     cells = L ** 3
     value = cells / (ms * 1e-3) / 1e9
     bpc = BYTES_PER_CELL[a.storage]
@@ -170,13 +174,26 @@ def main():
                 launches_timed=launches, ms_per_launch=round(per_launch, 5),
                 per_pass=dict(bytes=bpc * cells, gbs=round(per_pass, 1), frac=round(per_pass / HBM_PEAK_GBS, 4)))
 
+    # Reduced-precision storage: timed over the last variant_steps of the same
+    # number of steps as the FP64 run, then compared with the FP64 state (which
+    # is bitwise the FP64 definition's) field by field.
     variants = {}
     for sv in [x for x in a.variants.split(",") if x and x not in (a.storage, "none")]:
-        vms, _, _, vcfg, vd = measure(sv, a.variant_steps, a.warmup)
+        total = a.warmup + a.steps
+        vsteps = min(a.variant_steps, total)
+        vms, _, _, vcfg, vd, vuv = measure(sv, vsteps, total - vsteps, fields=want_err)
         vach = BYTES_PER_CELL[sv] * cells / (vms * 1e-3) / 1e9
         variants[sv] = dict(value=round(cells / (vms * 1e-3) / 1e9, 3), ms_per_step=round(vms, 5),
-                            algorithmic_gbs=round(vach, 1), frac=round(vach / HBM_PEAK_GBS, 4), steps=a.variant_steps,
+                            algorithmic_gbs=round(vach, 1), frac=round(vach / HBM_PEAK_GBS, 4), steps_timed=vsteps,
                             bytes_per_cell=BYTES_PER_CELL[sv], launch_config=vcfg)
+        if want_err:
+            err = {}
+            for name, x, y in (("u", vuv[0], ref[0]), ("v", vuv[1], ref[1])):
+                dlt = x - y
+                err[f"{name}_maxabs"] = float(abs(dlt).max())
+                err[f"{name}_rms"] = float(math.sqrt(float((dlt * dlt).mean())))
+            variants[sv]["error_vs_f64"] = dict(after_steps=total, **{k: float(f"{v:.3e}") for k, v in err.items()})
+            del vuv
 
     cpu = None
     if not a.no_cpu_baseline:
