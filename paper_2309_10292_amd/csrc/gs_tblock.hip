@@ -34,14 +34,38 @@ template <typename S, int TXG, int TY, int T, int NT> struct TbGeom {
     static constexpr int GX = TXG + 2;          // x-groups per region row
     static constexpr int RW = GX * 4;           // region row width (cells)
     static constexpr int H = 16 / (int)sizeof(C);  // LDS row pad (>= 1; keeps rows 16-byte aligned)
-    static constexpr int RS = RW + 2 * H;       // LDS row stride
     static constexpr int RY0 = TY + 2 * T;      // level-0 rows
     static constexpr int NSLOT = GX * RY0;      // lanes with a level-0 position
     // LDS rows of levels 0..T-1: RY0 - 2k each.
     static constexpr int LDS_ROWS = T * RY0 - T * (T - 1);
+    // FP64 rows are split in two half-rows: cells 0-1 of every x-group, then
+    // cells 2-3. A lane's four cells are 32 bytes, and 16-byte LDS accesses at
+    // a 32-byte lane stride conflict in the banks; in half-rows every 16-byte
+    // access of a row of lanes is contiguous. Each half-row has a pad group on
+    // either side for the x-neighbours at the region's edges. FP32 rows (16
+    // bytes per lane) are contiguous as they are.
+    static constexpr bool SPLIT = sizeof(C) == 8;
+    static constexpr int HS = 2 * (GX + 2);     // half-row length
+    static constexpr int RS_MIN = SPLIT ? 2 * HS : RW + 2 * H;
+    // A wave holds several rows of 16 lanes; their 16-byte reads are free of
+    // bank conflicts on gfx950 only when the rows start a multiple of 256
+    // bytes apart (measured with the LDS counters; 640- and 320-byte strides
+    // conflict two ways). Rows are padded to that where the padded planes fit
+    // the LDS of a CU.
+    static constexpr int RS_PAD = (int)((RS_MIN * sizeof(C) + 255) / 256 * 256 / sizeof(C));
+    static constexpr int RS = 2 * LDS_ROWS * RS_PAD * sizeof(C) <= 160 * 1024 ? RS_PAD : RS_MIN; // row stride
+    // Offset within a row of column 4 gx + e of the region (e = -1 .. 4):
+    // a per-lane base plus a constant, so every access of a lane shares one
+    // address register.
+    static __host__ __device__ constexpr int lane_base(int gx) { return SPLIT ? 2 * (gx + 1) : H + 4 * gx; }
+    static __host__ __device__ constexpr int cell_off(int e)
+    {
+        return SPLIT ? (e < 0 ? HS - 1 : e < 2 ? e : e < 4 ? HS + e - 2 : 2) : e;
+    }
     static constexpr int FIELD = LDS_ROWS * RS; // elements per field
     static_assert(T >= 1 && T <= 4, "one pad group covers at most 4 levels");
     static_assert(NSLOT <= NT, "every level-0 position needs a lane");
+    static_assert(2 * FIELD * sizeof(C) <= 160 * 1024, "staged planes fit the LDS of a CU");
     static constexpr int row_base(int k) { return k * RY0 - k * (k - 1); }
 };
 
@@ -180,8 +204,10 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
         for (int f = 0; f < 2; ++f) o[f] = *reinterpret_cast<const Vec<S, 4> *>(src[f] + off);
     };
-    auto lds_at = [&](int f, int k, int row, int col) -> C & {
-        return lds[f * G::FIELD + (G::row_base(k) + row) * G::RS + G::H + col];
+    const int lbase = G::lane_base(gxs);
+    // Element e (-1 .. 4, column 4 gxs + e) of row `row` of level k's plane.
+    auto lds_at = [&](int f, int k, int row, int e) -> C & {
+        return lds[f * G::FIELD + (G::row_base(k) + row) * G::RS + lbase + G::cell_off(e)];
     };
     auto in_level = [&](int k) { return dep >= k; };
 
@@ -205,7 +231,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][0][f][e];
+            for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, e) = win[0][0][f][e];
     }
     __syncthreads();
 
@@ -242,10 +268,10 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                 const C *c = win[k - 1][sc][f];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    xm[f][e] = e > 0 ? c[e - 1] : lds_at(f, k - 1, row, 4 * gxs - 1);
-                    xp[f][e] = e < 3 ? c[e + 1] : lds_at(f, k - 1, row, 4 * gxs + 4);
-                    ym[f][e] = lds_at(f, k - 1, row - 1, 4 * gxs + e);
-                    yp[f][e] = lds_at(f, k - 1, row + 1, 4 * gxs + e);
+                    xm[f][e] = e > 0 ? c[e - 1] : lds_at(f, k - 1, row, -1);
+                    xp[f][e] = e < 3 ? c[e + 1] : lds_at(f, k - 1, row, 4);
+                    ym[f][e] = lds_at(f, k - 1, row - 1, e);
+                    yp[f][e] = lds_at(f, k - 1, row + 1, e);
                 }
             }
             C r[4] = {(C)0, (C)0, (C)0, (C)0}; // FP64: the noise term n r; FP32: r
@@ -306,7 +332,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
             for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, 4 * gxs + e) = win[0][slot3(P + 1)][f][e];
+                for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, e) = win[0][slot3(P + 1)][f][e];
         }
 #pragma unroll
         for (int k = 1; k < T; ++k) {
@@ -314,7 +340,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
                 for (int f = 0; f < 2; ++f)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, 4 * gxs + e) = win[k][slot3(P - k + 1)][f][e];
+                    for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, e) = win[k][slot3(P - k + 1)][f][e];
             }
         }
         __syncthreads();
