@@ -227,12 +227,11 @@ gs_status check(gs_sim *s)
 // Library choice of the launch configuration before any tuning (from the
 // MI355X autotuner sweeps at 512^3 and 1024^3): large grids use the
 // temporally blocked kernel: FP64 with three fused steps (64 x 22 tiles, 512
-// lanes, 128-plane chunks), FP32 with two (the compensated Laplacian makes
-// deeper fusion arithmetic-bound): 512 lanes and 64-plane chunks without
-// noise, 1024 lanes and 32-plane chunks with noise (whose Philox work wants
-// more waves per SIMD); FP16 with one step in 768-lane workgroups; BF16 keeps
-// the single-step kernel. Small grids keep the single-step kernel with short
-// chunks so that enough workgroups exist.
+// lanes), FP32 with two (the compensated Laplacian makes deeper fusion
+// arithmetic-bound): 512 lanes without noise, 1024 lanes with noise (whose
+// Philox work wants more waves per SIMD); FP16 with one step in 768-lane
+// workgroups; BF16 keeps the single-step kernel. Small grids keep the
+// single-step kernel.
 bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
@@ -252,8 +251,49 @@ int default_tblock(const gs_params &p, int tile)
     return T < mt ? T : mt;
 }
 
-int default_zc(const gs_params &p, int tile)
+// z-chunks the autotuner sweeps.
+const int k_zchunks[] = {16, 32, 64, 128, 256, 512};
+
+// Default z-chunk: a workgroup of a chunk of zc output planes streams
+// zc + 2T planes, and nb workgroups on `slots` resident places (CUs times
+// workgroups per CU) take ceil(nb / slots) rounds, so the sweep costs about
+// ceil(nb / slots) (zc + 2T) plane times; the partly filled last round costs
+// up to a fifth of the throughput at 512^3 with a fixed chunk. Chunks that
+// leave fewer than three rounds are slower than this predicts (every CU then
+// starts and drains its workgroups at once), so the cheapest chunk with at
+// least three rounds is taken (the larger one on ties), else the shortest
+// chunk. The single-step kernel keeps chunks of at most 32 planes (longer
+// ones measured slower at 1024^3 although the estimate favours them).
+// Without the occupancy figures it falls back to fixed chunks.
+int default_zc(const gs_params &p, int tile, int tblock)
 {
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    const bool tb = is_tb_tile(tile);
+    const int occ = tb ? gs::tb_occupancy(p.storage, tblock, tile - gs::num_tiles(), p.noise != 0.0)
+                       : gs::step_occupancy(p.storage, tile, p.noise != 0.0);
+    const gs::TileShape t = tb ? gs::tb_shape(tile - gs::num_tiles(), tblock) : gs::tile_shape(tile, p.storage);
+    if (cus > 0 && occ > 0 && t.tx > 0 && t.ty > 0) {
+        const double slots = (double)cus * occ;
+        const double tiles = (double)((p.nx + t.tx - 1) / t.tx) * (double)((p.ny + t.ty - 1) / t.ty);
+        const int T = tb ? tblock : 1;
+        double best = 1e300;
+        int bz = 0;
+        for (int z : k_zchunks) {
+            const int zc = z < p.nz ? z : p.nz;
+            const double nb = tiles * (double)((p.nz + zc - 1) / zc);
+            if (nb < 3.0 * slots || (!tb && z > 32)) continue;
+            const double cost = std::ceil(nb / slots) * (double)(zc + 2 * T);
+            if (cost <= best) {
+                best = cost;
+                bz = zc;
+            }
+        }
+        if (bz == 0) bz = k_zchunks[0] < p.nz ? k_zchunks[0] : p.nz;
+        return bz;
+    }
     int z = 16;
     if (large_grid(p))
         z = tile <= gs::num_tiles() ? 32 : p.storage == GS_F64 ? 128 : (p.storage == GS_F32 && p.noise != 0.0) ? 32 : 64;
@@ -388,8 +428,8 @@ gs_status gs_init(const gs_params *p, void *u0, void *v0, void *u1, void *v1, vo
     s->ws = workspace;
     s->stream = (hipStream_t)hip_stream;
     s->tile = p->tile ? p->tile : default_tile(*p);
-    s->zc = p->zchunk ? (p->zchunk < p->nz ? p->zchunk : p->nz) : default_zc(*p, s->tile);
     s->tblock = p->tblock ? p->tblock : default_tblock(*p, s->tile);
+    s->zc = p->zchunk ? (p->zchunk < p->nz ? p->zchunk : p->nz) : default_zc(*p, s->tile, s->tblock);
     if (p->tile == 0 && p->tblock == 0 && p->zchunk == 0) {
         // a configuration recorded by gs_tune for this grid class, if any
         TuneVal v;
@@ -531,7 +571,7 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
     if (st != GS_OK) return st;
     if (reps < 1) return fail(GS_ERR_INVALID_ARG, "reps %d < 1", reps);
     if (capacity < 0 || (capacity > 0 && !table)) return fail(GS_ERR_INVALID_ARG, "bad table/capacity");
-    static const int zcs[] = {16, 32, 64, 128, 256, 512};
+    const int *zcs = k_zchunks;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -546,7 +586,7 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
     for (int tile = 1; tile <= total_tiles() && e == hipSuccess; ++tile) {
         for (int T = 1; T <= tile_max_tblock(tile, s->p.storage) && e == hipSuccess; ++T) {
             int last_zc = -1;
-            for (int zi = 0; zi < (int)(sizeof zcs / sizeof zcs[0]) && e == hipSuccess; ++zi) {
+            for (int zi = 0; zi < (int)(sizeof k_zchunks / sizeof k_zchunks[0]) && e == hipSuccess; ++zi) {
                 const int zc = zcs[zi] < s->p.nz ? zcs[zi] : s->p.nz;
                 if (zc == last_zc) continue;
                 last_zc = zc;

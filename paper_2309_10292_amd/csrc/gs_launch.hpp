@@ -52,6 +52,8 @@ TileShape tile_shape(int tile, int storage);
 // One step (u, v) -> (un, vn) with the given tile (1..num_tiles()).
 hipError_t launch_step(int storage, int tile, const void *u, const void *v, void *un, void *vn,
                        const StepArgs &a, hipStream_t st);
+// Resident workgroups per CU of the single-step kernel (0 when unknown).
+int step_occupancy(int storage, int tile, bool noise);
 
 hipError_t launch_laplacian7(const double *f, double *out, int nx, int ny, int nz, hipStream_t st);
 
@@ -122,4 +124,6 @@ hipError_t launch_tblock_batch(int storage, int T, int shape, const BatchArgs &b
 int tb_shape_lanes(int shape);
 // Resident workgroups per CU of the batched kernel (at least 1).
 int tb_batch_occupancy(int storage, int T, int shape);
+// Resident workgroups per CU of the single-grid blocked kernel (0 when unknown).
+int tb_occupancy(int storage, int T, int shape, bool noise);
 } // namespace gs

@@ -316,6 +316,49 @@ static hipError_t dispatch_w8(int tile, const void *u, const void *v, void *un, 
     return hipErrorInvalidValue;
 }
 
+template <typename S, int TX, int TY, int V>
+static int occ_step_t(bool noise)
+{
+    int n = 0;
+    const hipError_t e =
+        noise ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stencil_tile<S, TX, TY, V, 2, true, false>, 256, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stencil_tile<S, TX, TY, V, 2, false, false>, 256, 0);
+    return e == hipSuccess && n > 0 ? n : 0;
+}
+
+template <typename S> static int occ_w4(int tile, bool noise)
+{
+    switch (tile) {
+    case 1: return occ_step_t<S, 64, 16, 4>(noise);
+    case 2: return occ_step_t<S, 128, 8, 4>(noise);
+    case 3: return occ_step_t<S, 32, 32, 4>(noise);
+    case 4: return occ_step_t<S, 256, 4, 4>(noise);
+    }
+    return 0;
+}
+
+template <typename S> static int occ_w8(int tile, bool noise)
+{
+    switch (tile) {
+    case 1: return occ_step_t<S, 128, 16, 8>(noise);
+    case 2: return occ_step_t<S, 64, 32, 8>(noise);
+    case 3: return occ_step_t<S, 256, 8, 8>(noise);
+    case 4: return occ_step_t<S, 32, 64, 8>(noise);
+    }
+    return 0;
+}
+
+int step_occupancy(int storage, int tile, bool noise)
+{
+    switch (storage) {
+    case 0: return occ_w4<double>(tile, noise);
+    case 1: return occ_w4<float>(tile, noise);
+    case 2: return occ_w8<bf16>(tile, noise);
+    case 3: return occ_w8<f16>(tile, noise);
+    }
+    return 0;
+}
+
 hipError_t launch_step(int storage, int tile, const void *u, const void *v, void *un, void *vn,
                        const StepArgs &a, hipStream_t st)
 {

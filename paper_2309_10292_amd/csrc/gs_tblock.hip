@@ -628,6 +628,56 @@ static int occ_T(int T, int shape)
     return 1;
 }
 
+template <typename S, int TXG, int TY, int T, int NT>
+static int occ_single_t(bool noise)
+{
+    int n = 0;
+    const hipError_t e = noise
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stencil_tb<S, TXG, TY, T, NT, true>, NT, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, stencil_tb<S, TXG, TY, T, NT, false>, NT, 0);
+    return e == hipSuccess && n > 0 ? n : 0;
+}
+
+template <typename S, int T>
+static int occ_single_shape(int shape, bool noise)
+{
+    switch (shape) {
+    case 1: return occ_single_t<S, 16, 14 - 2 * T, T, 256>(noise);
+    case 2: return occ_single_t<S, 16, 28 - 2 * T, T, 512>(noise);
+    case 3: return occ_single_t<S, 32, 14 - 2 * T, T, 512>(noise);
+    case 4:
+        if constexpr (T <= tb_max_T_of<S, 768, false>()) return occ_single_t<S, 16, 42 - 2 * T, T, 768>(noise);
+        break;
+    case 5:
+        if constexpr (T <= tb_max_T_of<S, 1024, false>()) return occ_single_t<S, 16, 56 - 2 * T, T, 1024>(noise);
+        break;
+    }
+    return 0;
+}
+
+template <typename S>
+static int occ_single_T(int T, int shape, bool noise)
+{
+    switch (T) {
+    case 1: return occ_single_shape<S, 1>(shape, noise);
+    case 2: return occ_single_shape<S, 2>(shape, noise);
+    case 3: return occ_single_shape<S, 3>(shape, noise);
+    case 4: return occ_single_shape<S, 4>(shape, noise);
+    }
+    return 0;
+}
+
+int tb_occupancy(int storage, int T, int shape, bool noise)
+{
+    switch (storage) {
+    case 0: return occ_single_T<double>(T, shape, noise);
+    case 1: return occ_single_T<float>(T, shape, noise);
+    case 2: return occ_single_T<bf16>(T, shape, noise);
+    case 3: return occ_single_T<f16>(T, shape, noise);
+    }
+    return 0;
+}
+
 int tb_batch_occupancy(int storage, int T, int shape)
 {
     switch (storage) {
