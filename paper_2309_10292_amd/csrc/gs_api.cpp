@@ -321,6 +321,8 @@ gs::StepArgs make_args(const gs_sim *s)
     a.FK_f = (float)a.FK;
     a.dt_f = (float)a.dt;
     a.noise_f = (float)a.noise;
+    a.noise_s_f = (float)a.noise_s;
+    a.noise_h_f = (float)a.noise_h;
     a.seed = s->p.seed;
     a.t = s->step;
     a.t_dev = nullptr;

@@ -118,6 +118,8 @@ gs::StepArgs shared_coef(const gs_batch *b)
     a.Dv_f = (float)a.Dv;
     a.dt_f = (float)a.dt;
     a.noise_f = (float)a.noise;
+    a.noise_s_f = (float)a.noise_s;
+    a.noise_h_f = (float)a.noise_h;
     return a;
 }
 

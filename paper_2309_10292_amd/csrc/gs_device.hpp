@@ -53,7 +53,16 @@ template <> struct Traits<bf16> {
 template <> struct Traits<f16> {
     typedef float C;
     static __device__ __forceinline__ float load(f16 s) { return (float)s; }
-    static __device__ __forceinline__ f16 store(float c) { return (f16)c; }
+    // The empty asm hides the FP32 value before the conversion (no
+    // instruction): without it the compiler may fuse the conversion into the
+    // fma that produced the value (an fma_mix with an FP16 result), which
+    // rounds differently from the fma and then the conversion, and does so in
+    // some kernels and not in others.
+    static __device__ __forceinline__ f16 store(float c)
+    {
+        asm("" : "+v"(c));
+        return (f16)c;
+    }
 };
 
 // V consecutive storage elements moved as one aligned vector access.
@@ -103,9 +112,30 @@ __device__ __forceinline__ double noise_word_f64(uint32_t w)
 {
     return ((double)(int32_t)w + 0.5) * 0x1p-31;
 }
-__device__ __forceinline__ float noise_word_f32(uint32_t w)
+// FP32 noise term n r = (n 2^-31) w + n 2^-32 for the signed word w, as one
+// fma of the word converted to FP32 with the FP32 scales s = RN(n 2^-31),
+// h = RN(n 2^-32) (the word keeps 24 significant bits, below what FP32
+// storage resolves in the step).
+__device__ __forceinline__ float noise_term_f32(uint32_t w, float s, float h)
 {
-    return (float)(((double)(int32_t)w + 0.5) * 0x1p-31);
+    return __builtin_fmaf((float)(int32_t)w, s, h);
+}
+
+// One Euler step of a cell in FP32 arithmetic (storage other than FP64):
+// Eq. 1a/1b and 2a/2b with the products fused into the sums, so each field
+// takes three operations after u v^2. nr is the noise term n r (NOISE).
+// Every FP32 kernel uses this one sequence, so results do not depend on the
+// kernel, the tile or the fused depth.
+template <bool NOISE>
+__device__ __forceinline__ void euler_f32(float Du, float Dv, float F, float FK, float dt, float uc, float vc,
+                                          float lu, float lv, float nr, float &uo, float &vo)
+{
+    const float uvv = uc * (vc * vc);
+    float du = __builtin_fmaf(F, 1.0f - uc, __builtin_fmaf(Du, lu, -uvv));
+    if constexpr (NOISE) du = du + nr;
+    const float dv = __builtin_fmaf(-FK, vc, __builtin_fmaf(Dv, lv, uvv));
+    uo = __builtin_fmaf(du, dt, uc);
+    vo = __builtin_fmaf(dv, dt, vc);
 }
 
 // Noise of the 4 cells idx4 .. idx4+3 (idx4 a multiple of 4) at step t.

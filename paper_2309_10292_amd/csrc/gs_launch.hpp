@@ -15,6 +15,7 @@ struct StepArgs {
     double Du, Dv, F, FK, dt, noise;   // FK = F + k, rounded once
     double noise_s, noise_h;           // noise 2^-31 and noise 2^-32 (exact: |noise| >= 2^-990 or 0)
     float Du_f, Dv_f, F_f, FK_f, dt_f, noise_f;
+    float noise_s_f, noise_h_f;        // RN(noise 2^-31), RN(noise 2^-32) in FP32
     uint64_t seed;
     uint64_t t;          // global index of the step being taken (noise key)
     // When non-null, the step index is *t_dev + t (graph replays read the

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
                         if constexpr (sizeof(C) == 8)
                             r[4 * b + j] = noise_word_f64(w.w[j]);
                         else
-                            r[4 * b + j] = noise_word_f32(w.w[j]);
+                            r[4 * b + j] = noise_term_f32(w.w[j], a.noise_s_f, a.noise_h_f);
                     }
                 }
             }
@@ -219,14 +219,22 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
                     lu = lap_comp_f32(uc, xm[0][i], xp[0][i], ym[0][i], yp[0][i], zm[0][i], zp[0][i]);
                     lv = lap_comp_f32(vc, xm[1][i], xp[1][i], ym[1][i], yp[1][i], zm[1][i], zp[1][i]);
                 }
-                const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
-                const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
-                const C uvv = uc * (vc * vc);
-                C du = (Du * lu - uvv) + F * ((C)1 - uc);
-                if constexpr (NOISE) du = du + Coef<C>::noise(a) * r[i];
-                const C dv = (Dv * lv + uvv) - FK * vc;
-                ou.e[i] = Traits<S>::store(uc + du * dt);
-                ov.e[i] = Traits<S>::store(vc + dv * dt);
+                if constexpr (sizeof(C) == 4) {
+                    // the FP32 sequence shared with the blocked kernels; r is n r
+                    float uo, vo;
+                    euler_f32<NOISE>(a.Du_f, a.Dv_f, a.F_f, a.FK_f, a.dt_f, uc, vc, lu, lv, r[i], uo, vo);
+                    ou.e[i] = Traits<S>::store(uo);
+                    ov.e[i] = Traits<S>::store(vo);
+                } else {
+                    const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
+                    const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
+                    const C uvv = uc * (vc * vc);
+                    C du = (Du * lu - uvv) + F * ((C)1 - uc);
+                    if constexpr (NOISE) du = du + Coef<C>::noise(a) * r[i];
+                    const C dv = (Dv * lv + uvv) - FK * vc;
+                    ou.e[i] = Traits<S>::store(uc + du * dt);
+                    ov.e[i] = Traits<S>::store(vc + dv * dt);
+                }
             }
             if (m.valid) {
                 *reinterpret_cast<Vec<S, V> *>(un + out_off) = ou;

@@ -114,28 +114,28 @@ template <bool F> struct Full {
 __host__ __device__ constexpr int slot3(int p) { return ((p % 3) + 3) % 3; }
 
 // UNIT_DT: dt is exactly 1, so the products du dt and dv dt equal du and dv
-// (bitwise) and are skipped. In FP64, nr is the noise term n r itself; in
-// FP32 it is r.
-template <typename C, bool UNIT_DT>
-__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, bool noisy, C nr, C &uo, C &vo)
+// (bitwise) and are skipped. nr is the noise term n r. FP64 follows the
+// definition's operation order; FP32 arithmetic takes the fused sequence
+// shared by every FP32 kernel.
+template <typename C, bool UNIT_DT, bool NOISE>
+__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, C nr, C &uo, C &vo)
 {
-    const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
-    const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
-    const C uvv = uc * (vc * vc);
-    C du = (Du * lu - uvv) + F * ((C)1 - uc);
-    if (noisy) {
-        if constexpr (sizeof(C) == 8)
-            du = du + nr;
-        else
-            du = du + Coef<C>::noise(a) * nr;
-    }
-    const C dv = (Dv * lv + uvv) - FK * vc;
-    if constexpr (UNIT_DT) {
-        uo = uc + du;
-        vo = vc + dv;
+    if constexpr (sizeof(C) == 4) {
+        euler_f32<NOISE>(a.Du_f, a.Dv_f, a.F_f, a.FK_f, a.dt_f, uc, vc, lu, lv, nr, uo, vo);
     } else {
-        uo = uc + du * dt;
-        vo = vc + dv * dt;
+        const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
+        const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
+        const C uvv = uc * (vc * vc);
+        C du = (Du * lu - uvv) + F * ((C)1 - uc);
+        if constexpr (NOISE) du = du + nr;
+        const C dv = (Dv * lv + uvv) - FK * vc;
+        if constexpr (UNIT_DT) {
+            uo = uc + du;
+            vo = vc + dv;
+        } else {
+            uo = uc + du * dt;
+            vo = vc + dv * dt;
+        }
     }
 }
 
@@ -274,7 +274,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                     yp[f][e] = lds_at(f, k - 1, row + 1, e);
                 }
             }
-            C r[4] = {(C)0, (C)0, (C)0, (C)0}; // FP64: the noise term n r; FP32: r
+            C r[4] = {(C)0, (C)0, (C)0, (C)0}; // the noise term n r
             if constexpr (NOISE) {
                 const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
                 const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
@@ -286,7 +286,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                     if constexpr (sizeof(C) == 8)
                         r[e] = __builtin_fma(a.noise_s, (double)(int32_t)w.w[e], a.noise_h);
                     else
-                        r[e] = noise_word_f32(w.w[e]);
+                        r[e] = noise_term_f32(w.w[e], a.noise_s_f, a.noise_h_f);
                 }
             }
             C res[2][4];
@@ -304,7 +304,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                                       win[k - 1][sp][1][e]);
                 }
                 C uo, vo;
-                cell_update<C, UNIT_DT>(a, uc, vc, lu, lv, NOISE, r[e], uo, vo);
+                cell_update<C, UNIT_DT, NOISE>(a, uc, vc, lu, lv, r[e], uo, vo);
                 // Intermediate levels carry the stored precision of the state.
                 res[0][e] = Traits<S>::load(Traits<S>::store(uo));
                 res[1][e] = Traits<S>::load(Traits<S>::store(vo));
@@ -366,9 +366,21 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
     }
 }
 
+// Waves per SIMD the single-grid kernel is compiled for (its register
+// budget): with FP32 arithmetic and up to two fused steps the kernel fits 128
+// registers, so 256- and 512-lane workgroups keep four waves per SIMD (two
+// 512-lane workgroups per CU; one register more would leave one); other
+// kernels take what their lane count allows.
+template <typename S, int T, int NT> constexpr int tb_min_waves()
+{
+    return (sizeof(typename Traits<S>::C) == 4 && T <= 2 && NT <= 512) ? 4 : 1;
+}
+
 template <typename S, int TXG, int TY, int T, int NT, bool NOISE>
-__global__ __launch_bounds__(NT) void stencil_tb(const S *__restrict__ u, const S *__restrict__ v,
-                                                 S *__restrict__ un, S *__restrict__ vn, StepArgs a)
+__global__ __launch_bounds__(NT, (tb_min_waves<S, T, NT>())) void stencil_tb(const S *__restrict__ u,
+                                                                           const S *__restrict__ v,
+                                                                           S *__restrict__ un, S *__restrict__ vn,
+                                                                           StepArgs a)
 {
     typedef TbGeom<S, TXG, TY, T, NT> G;
     __shared__ typename G::C lds[2 * G::FIELD];
