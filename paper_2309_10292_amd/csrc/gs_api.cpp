@@ -227,19 +227,18 @@ gs_status check(gs_sim *s)
 // Library choice of the launch configuration before any tuning (from the
 // MI355X autotuner sweeps at 512^3 and 1024^3): large grids use the
 // temporally blocked kernel: FP64 with three fused steps (64 x 22 tiles, 512
-// lanes), FP32 with two (the compensated Laplacian makes deeper fusion
-// arithmetic-bound): 512 lanes without noise, 1024 lanes with noise (whose
-// Philox work wants more waves per SIMD); FP16 with one step in 768-lane
-// workgroups; BF16 keeps the single-step kernel. Small grids keep the
-// single-step kernel.
+// lanes), FP32 with two in the same shape (the compensated Laplacian makes
+// deeper fusion arithmetic-bound), FP16 with one step in 768-lane
+// workgroups, BF16 with one step in 256-lane workgroups when noise is on;
+// BF16 without noise keeps the single-step kernel, and so do small grids.
 bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
 {
     if (!large_grid(p)) return 1;
-    if (p.storage == GS_F64) return gs::num_tiles() + 2;
-    if (p.storage == GS_F32) return gs::num_tiles() + (p.noise != 0.0 ? 5 : 2);
+    if (p.storage == GS_F64 || p.storage == GS_F32) return gs::num_tiles() + 2;
     if (p.storage == GS_F16) return gs::num_tiles() + 4;
+    if (p.storage == GS_BF16 && p.noise != 0.0) return gs::num_tiles() + 1;
     return 1;
 }
 
@@ -296,7 +295,7 @@ int default_zc(const gs_params &p, int tile, int tblock)
     }
     int z = 16;
     if (large_grid(p))
-        z = tile <= gs::num_tiles() ? 32 : p.storage == GS_F64 ? 128 : (p.storage == GS_F32 && p.noise != 0.0) ? 32 : 64;
+        z = tile <= gs::num_tiles() ? 32 : p.storage == GS_F64 ? 128 : p.storage == GS_F32 ? 32 : 64;
     return p.nz < z ? p.nz : z;
 }
 
