@@ -19,17 +19,12 @@ __device__ __forceinline__ float to_f32(float x) { return x; }
 __device__ __forceinline__ float to_f32(f16 x) { return (float)x; }
 __device__ __forceinline__ float to_f32(bf16 x) { return __uint_as_float((uint32_t)x.bits << 16); }
 
-// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN).
+// Round-to-nearest-even FP32 -> BF16 (NaN stays NaN): one gfx950
+// conversion instruction.
 __device__ __forceinline__ bf16 bf16_rne(float f)
 {
-    uint32_t u = __float_as_uint(f);
     bf16 r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r.bits = (uint16_t)((u >> 16) | 0x40u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r.bits = (uint16_t)(u >> 16);
-    }
+    r.bits = __builtin_bit_cast(uint16_t, (__bf16)f);
     return r;
 }
 

@@ -24,10 +24,34 @@ typedef uint16_t u16;
 __device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ u16 f2bf(float f) { return bf16_rne(f).bits; }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun 7.1.26 (Hastings' rational approximation,
+// |error| <= 1.5e-7, far below the BF16 rounding of the activations),
+// without branches; e receives exp(-x^2), which the GELU's derivative reuses.
+__device__ __forceinline__ float erf_as(float x, float &e)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.0f));
+    float p = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+    p = __builtin_fmaf(p, t, 1.421413741f);
+    p = __builtin_fmaf(p, t, -0.284496736f);
+    p = __builtin_fmaf(p, t, 0.254829592f);
+    p *= t;
+    e = __expf(-ax * ax);
+    return copysignf(__builtin_fmaf(-p, e, 1.0f), x);
+}
+
+// GELU(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2 and its derivative
+// Phi(z) + z phi(z), phi(z) = exp(-z^2 / 2) / sqrt(2 pi).
+__device__ __forceinline__ float gelu(float z)
+{
+    float e;
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, e));
+}
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    float e;
+    const float er = erf_as(z * 0.70710678118654752f, e);
+    return __builtin_fmaf(0.5f, 1.0f + er, z * e * 0.39894228040143268f);
 }
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
