@@ -251,7 +251,7 @@ int default_tblock(const gs_params &p, int tile)
 }
 
 // z-chunks the autotuner sweeps.
-const int k_zchunks[] = {16, 32, 64, 128, 256, 512};
+const int k_zchunks[] = {4, 8, 16, 32, 64, 128, 256, 512};
 
 // Default z-chunk: a workgroup of a chunk of zc output planes streams
 // zc + 2T planes, and nb workgroups on `slots` resident places (CUs times

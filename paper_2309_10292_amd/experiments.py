@@ -8,11 +8,15 @@ JSON record (and writing it to --out):
              0.07], L ~ U{32, 48, ..., 192}), cube start, 500 steps, FP64:
              one persistent batched sweep (default and autotuned, graph
              replay) against the same simulations run one after another.
+  small      the L=64 parity workload (FP64, 100 steps): eager launches
+             against one captured HIP graph replayed. Its 8 MB of state stay
+             in the caches, so this is launch and latency cost, not an HBM
+             figure.
   surrogate  the 16-step surrogate trained on stencil trajectories at L=128
              and run with the stencil-fallback controller, against the plain
              FP64 stencil on the same GPU.
 
-    python -m paper_2309_10292_amd.experiments precision|batched|surrogate [--out FILE]
+    python -m paper_2309_10292_amd.experiments precision|batched|small|surrogate [--out FILE]
 """
 from __future__ import annotations
 
@@ -66,6 +70,33 @@ def precision(args):
                    sum_u=d["sum_u"], sum_v=d["sum_v"], nonfinite=d["nonfinite"])
         out["storage"][storage] = rec
         print(json.dumps({storage: rec}), flush=True)
+    return out
+
+
+def small(args):
+    """The L=64 parity workload: 100 FP64 steps launched one by one, and
+    the same steps replayed from one captured HIP graph (median of 20 runs
+    each, after a warm-up)."""
+    import torch
+    from paper_2309_10292_amd import gs
+    from synth import workload
+    p = workload("small_l64")
+    L, n, side = p["L"], p["steps"], p["cube_side"]
+    kw = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise")}
+    out = dict(experiment="small", workload=f"periodic {L}^3, FP64, {n} steps, noise 0", steps=n)
+    with gs.Sim(L, L, L, storage="f64", cube_side=side, **kw) as s:
+        if args.tune:
+            s.tune(reps=3)
+        out["launch"] = s.config()
+        launches = -(-n // out["launch"]["tblock"])
+        for mode, fn in (("eager", lambda: s.step(n)), ("graph", lambda: s.step_graph(n))):
+            fn()
+            t = sorted(_timed(torch, fn) for _ in range(20))
+            ms = t[len(t) // 2]
+            out[mode] = dict(ms=round(ms, 4), us_per_step=round(ms * 1e3 / n, 2),
+                             gcells=round(L ** 3 * n / (ms * 1e-3) / 1e9, 2))
+        out["launches_per_run"] = launches
+        print(json.dumps(out), flush=True)
     return out
 
 
@@ -236,7 +267,7 @@ def surrogate(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["precision", "batched", "surrogate"])
+    ap.add_argument("which", choices=["precision", "batched", "small", "surrogate"])
     ap.add_argument("--out", default=None)
     ap.add_argument("--storages", default="f64,f32,bf16,f16")
     ap.add_argument("--tune", action="store_true")
@@ -256,7 +287,7 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--save", default=None, help="save the trained parameters (.npy)")
     a = ap.parse_args(argv)
-    res = {"precision": precision, "batched": batched, "surrogate": surrogate}[a.which](a)
+    res = {"precision": precision, "batched": batched, "small": small, "surrogate": surrogate}[a.which](a)
     s = json.dumps(res)
     print(s)
     if a.out:
