@@ -134,26 +134,44 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
         f32x4 acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 9
-        for (int c = 0; c < NCH; ++c) {
-            const int k0 = 32 * c + 8 * quad;
-            const int d = k0 / CIN, ci0 = k0 % CIN;
-            bf16x8 av;
-            if (d < 27) {
-                const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
-                const int slot = (((z + dz - 1) % 3) + 3) % 3;
-                const int cell = (wave + dy) * RX + col + dx;
-                av = __builtin_bit_cast(bf16x8, ring[slot * PLANE_V + cell * VPC + ci0 / 8]);
-            } else {
-                av = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
-            }
+        // A = weights (rows: output channels), B = activations (columns:
+        // cells), so a lane's accumulators are 4 consecutive output channels
+        // of one cell.
+        if constexpr (CIN == 32) {
+            // K chunk c is offset d = c with all 32 input channels: one ring
+            // slot per dz, its nine (dy, dx) offsets unrolled.
+            for (int dz = 0; dz < 3; ++dz) {
+                const uint4 *rs = ring + ((z + dz + 2) % 3) * PLANE_V; // slot of plane z + dz - 1
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                // A = weights (rows: output channels), B = activations (columns:
-                // cells), so a lane's accumulators are 4 consecutive output
-                // channels of one cell.
-                const bf16x8 wv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
+                for (int j = 0; j < 9; ++j) {
+                    const int dy = j / 3, dx = j % 3, c = 9 * dz + j;
+                    const bf16x8 av = __builtin_bit_cast(bf16x8, rs[((wave + dy) * RX + col + dx) * VPC + quad]);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const bf16x8 wv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 9
+            for (int c = 0; c < NCH; ++c) {
+                const int k0 = 32 * c + 8 * quad;
+                const int d = k0 / CIN, ci0 = k0 % CIN;
+                bf16x8 av;
+                if (d < 27) {
+                    const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
+                    const int slot = (((z + dz - 1) % 3) + 3) % 3;
+                    const int cell = (wave + dy) * RX + col + dx;
+                    av = __builtin_bit_cast(bf16x8, ring[slot * PLANE_V + cell * VPC + ci0 / 8]);
+                } else {
+                    av = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const bf16x8 wv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
+                }
             }
         }
         // acc[t][j]: output channel 16 t + 4 quad + j of cell (x0 + col, yrow, z).
