@@ -260,11 +260,13 @@ def max_T(tile, storage):
     return gs.max_tblock(tile, storage)
 
 
+@pytest.mark.parametrize("zc", [3, 8, 16])
 @pytest.mark.parametrize("T", [1, 2, 3, 4])
-def test_tblock_bitwise_vs_oracle(torch, T):
+def test_tblock_bitwise_vs_oracle(torch, T, zc):
     """The temporally blocked kernel (T steps per pass, every shape) against the
     oracle on ragged periodic grids with noise; step counts that are not
-    multiples of T exercise the remainder launch."""
+    multiples of T exercise the remainder launch, and z-chunks shorter than
+    T (3 planes) the wavefront's prologue and epilogue overlapping."""
     for shape in [(20, 36, 40), (9, 13, 24), (70, 5, 16), (4, 4, 8)]:
         u0, v0 = random_state(shape, seed=7 * T + sum(shape), lo_u=0.2, hi_u=1.0, lo_v=0.0, hi_v=0.5)
         p = dict(Du=0.19, Dv=0.11, F=0.029, k=0.055, dt=0.9, noise=0.01, seed=4242, step0=77)
@@ -273,11 +275,11 @@ def test_tblock_bitwise_vs_oracle(torch, T):
         for tile in tb_tiles():
             if T > max_T(tile, "f64"):
                 continue
-            with _sim(shape, u0=u0, v0=v0, tile=tile, tblock=T, zchunk=16, **p) as s:
+            with _sim(shape, u0=u0, v0=v0, tile=tile, tblock=T, zchunk=zc, **p) as s:
                 s.step(n)
                 u, v = s.read()
             assert np.array_equal(u, ue) and np.array_equal(v, ve), \
-                f"T={T} tile={tile} shape={shape}: {max_abs(u, ue)} {max_abs(v, ve)}"
+                f"T={T} zc={zc} tile={tile} shape={shape}: {max_abs(u, ue)} {max_abs(v, ve)}"
 
 
 def test_tblock_small_l64_fp64_bitwise(torch, small_ref):
