@@ -131,24 +131,29 @@ def test_fixed_point_all_storage_types(torch):
         assert np.all(u == 1.0) and np.all(v == 0.0), storage
 
 
-def test_bf16_rounding_ties_to_even(torch):
-    """BF16 storage rounds FP32 to nearest, ties to even, on the device:
-    cube values exactly halfway between two BF16 neighbours land on the one
-    with the even significand, and a value just above a tie rounds up."""
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_16bit_rounding_ties_to_even(torch, storage):
+    """16-bit storage rounds FP32 to nearest, ties to even, on the device:
+    cube values exactly halfway between two neighbours of the format land on
+    the one with the even significand, and a value just above a tie rounds
+    up."""
     def rne(x):
+        if storage == "f16":
+            return float(np.float16(np.float32(x)))
         b = int(np.array([x], dtype=np.float32).view(np.uint32)[0])
         b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
         return float(np.array([b << 16], dtype=np.uint32).view(np.float32)[0])
 
-    cases = [(1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8),          # ties: 1 and 1 + 2^-6
-             (1 + 2.0 ** -8 + 2.0 ** -20, 0.25 + 2.0 ** -10)]  # above a tie: 1 + 2^-7; tie: 0.25
-    expect = [(1.0, 1 + 2.0 ** -6), (1 + 2.0 ** -7, 0.25)]
+    h = 2.0 ** -8 if storage == "bf16" else 2.0 ** -11  # half the spacing just above 1
+    cases = [(1 + h, 1 + 3 * h),                  # ties: 1 and 1 + 4h
+             (1 + h + 2.0 ** -20, 0.25 + h / 4)]  # just above a tie: 1 + 2h; a tie at 0.25: 0.25
+    expect = [(1.0, 1 + 4 * h), (1 + 2 * h, 0.25)]
     for (cu, cv), (eu, ev) in zip(cases, expect):
         assert (rne(cu), rne(cv)) == (eu, ev)
-        with _sim((16, 16, 16), storage="bf16", cube_side=4, cube_u=cu, cube_v=cv) as s:
+        with _sim((16, 16, 16), storage=storage, cube_side=4, cube_u=cu, cube_v=cv) as s:
             u, v = s.read()
         c = slice(6, 10)
-        assert np.all(u[c, c, c] == eu) and np.all(v[c, c, c] == ev), (cu, cv)
+        assert np.all(u[c, c, c] == eu) and np.all(v[c, c, c] == ev), (storage, cu, cv)
         assert np.all(u[:6] == 1.0) and np.all(v[:6] == 0.0)
 
 
