@@ -29,6 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_CELL = {"f64": 32, "f32": 16, "bf16": 8, "f16": 8}  # read u,v + write u,v once per step
+# Vector issue peak of MI355X: 256 CUs x 4 SIMDs, one wave64 instruction per
+# SIMD every 4 cycles (64 lanes) at 2.4 GHz = 39.3 T lane-instructions/s.
+VALU_PEAK_TOPS = 256 * 4 * 64 / 4 * 2.4e9 / 1e12
+# Vector instructions the method itself needs per FP64 cell-update: 36 FP64
+# operations (two Laplacians with the exact division by 6, the reaction, the
+# Euler update) and, with noise, 12 more (a Philox4x32-10 block per 4 cells:
+# 10 rounds of two 32x32->64-bit products and two three-input XORs, then the
+# word's conversion and the fused noise term).
+
+
+def alu_ops_per_cell_update(storage, noise):
+    return 36 + (12 if noise else 0) if storage == "f64" else None
 
 
 def parse():
@@ -173,6 +185,14 @@ def main():
                 cell_updates_per_launch=updates, algorithmic_bytes_per_launch=bpc * updates,
                 launches_timed=launches, ms_per_launch=round(per_launch, 5),
                 per_pass=dict(bytes=bpc * cells, gbs=round(per_pass, 1), frac=round(per_pass / HBM_PEAK_GBS, 4)))
+    # The secondary roof, vector issue: the method's own instructions per
+    # cell-update against the VALU peak (the kernel issues more: the halo
+    # rows of the fused levels and address arithmetic).
+    ops = alu_ops_per_cell_update(a.storage, p["noise"] != 0.0)
+    if ops is not None:
+        alu = ops * updates / (per_launch * 1e-3) / 1e12
+        roof["alu"] = dict(ops_per_cell_update=ops, achieved=round(alu, 2), peak=round(VALU_PEAK_TOPS, 2),
+                           unit="T lane-instructions/s", frac=round(alu / VALU_PEAK_TOPS, 4))
 
     # Reduced-precision storage: timed over the last variant_steps of the same
     # number of steps as the FP64 run, then compared with the FP64 state (which
