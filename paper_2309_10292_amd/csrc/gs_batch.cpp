@@ -536,7 +536,7 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
         Key k{s.nx, s.ny, s.nz};
         if (std::find(classes.begin(), classes.end(), k) == classes.end()) classes.push_back(k);
     }
-    static const int zcs[] = {16, 32, 64, 128};
+    static const int zcs[] = {k_min_batch_zc, 16, 32, 64, 128};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool cache_ok = true;
     hipError_t e = hipEventCreate(&e0);
