@@ -140,6 +140,10 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
         if constexpr (CIN == 32) {
             // K chunk c is offset d = c with all 32 input channels: one ring
             // slot per dz, its nine (dy, dx) offsets unrolled.
+            // Rolled in the forward hidden layer, unrolled elsewhere (each
+            // measured the faster there).
+            constexpr int DZ_UNROLL = MODE == MODE_HIDDEN ? 1 : 3;
+#pragma unroll DZ_UNROLL
             for (int dz = 0; dz < 3; ++dz) {
                 const uint4 *rs = ring + ((z + dz + 2) % 3) * PLANE_V; // slot of plane z + dz - 1
 #pragma unroll
