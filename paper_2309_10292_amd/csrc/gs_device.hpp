@@ -142,20 +142,39 @@ __device__ __forceinline__ Philox4 noise_block(uint64_t idx4, uint64_t t, uint64
 }
 
 // ---------------------------------------------------------------- arithmetic
-// Correctly rounded x / 6 without the FP64 divide sequence. With h = RN(1/6)
-// and q0 = RN(x h), the residual r = x - 6 q0 is a small multiple of ulp(q0)
-// and so exact in one fma, and RN(q0 + r h) == RN(x / 6): x / 6 = m ulp(x) / 6
-// for an integer m, and such a value is never closer than ulp(x) / 48 to a
-// rounding boundary of the result (odd multiples of ulp(x) / 16 or / 8, which
-// would need m divisible by 3 and an even multiplier at once), whereas
-// q0 + r h - x / 6 = r (h - 1/6) is below 2 ulp(x) * 2^-56. Valid for x in
-// the normal range away from overflow, which covers the Laplacian's argument.
-__device__ __forceinline__ double div6(double x)
+// Correctly rounded x / 6 without the FP64 divide sequence: the IEEE
+// quotient, bit for bit, for every finite x (a zero gives +0).
+//
+// With h = RN(1/6) and q0 = RN(x h), the residual r = x - 6 q0 is a small
+// multiple of ulp(q0) and so exact in one fma, and x / 6 = q0 + r / 6.
+// f = RN(q0 + r h) rounds that sum with r h in place of r / 6, off by
+// r (h - 1/6). Where the quotient is normal, x / 6 = m ulp(x) / 6 for an
+// integer m is never closer than ulp(x) / 48 to a rounding boundary (odd
+// multiples of ulp(x) / 16 or / 8, which would need m divisible by 3 and an
+// even multiplier at once), while r (h - 1/6) is below 2 ulp(x) 2^-56, so f
+// is the quotient. Where it is subnormal, its grid is the fixed step 2^-1074
+// and x / 6 can lie exactly half-way between two grid points (x an odd
+// multiple of 3 2^-1074); the small perturbation then decides the rounding
+// instead of the tie rule, and f lands on q0 whatever its parity. Such
+// arguments are common: a field decaying towards 0 has subnormal tails.
+//
+// The tie is resolved without a branch: t = RN(q0 + r h') with h' the
+// double just above 1/6 (h is just below) rounds the same as f except on an
+// exact tie, where f and t are the two grid points around x / 6. Then
+// RN(f + (t - f) / 2), formed as one fma of the exact difference f - t, is f
+// away from ties and the tie x / 6 itself rounded to even. The fma's
+// product is -0 when f == t, which keeps a -0 quotient of a tiny negative x.
+// A numerator of +-Inf (an infinite input, or a neighbour sum beyond the
+// largest double) gives NaN where the division gives +-Inf.
+__host__ __device__ __forceinline__ double div6(double x)
 {
-    const double h = 1.0 / 6.0;
+    const double h = 0x1.5555555555555p-3;  // RN(1/6), just below 1/6
+    const double hu = 0x1.5555555555556p-3; // the next double, just above 1/6
     const double q0 = x * h;
     const double r = __builtin_fma(-q0, 6.0, x);
-    return __builtin_fma(r, h, q0);
+    const double f = __builtin_fma(r, h, q0);
+    const double t = __builtin_fma(r, hu, q0);
+    return __builtin_fma(f - t, -0.5, f);
 }
 
 // Knuth's TwoSum: s + e == a + b exactly.
@@ -182,8 +201,8 @@ __device__ __forceinline__ float lap_comp_f32(float c, float xm, float xp, float
 
 // FP64 Laplacian in the canonical order: ((x- + x+) + (y- + y+)) + (z- + z+),
 // then (sum - 6 c) / 6.
-__device__ __forceinline__ double lap_f64(double c, double xm, double xp, double ym, double yp,
-                                          double zm, double zp)
+__host__ __device__ __forceinline__ double lap_f64(double c, double xm, double xp, double ym, double yp,
+                                                   double zm, double zp)
 {
     const double s = ((xm + xp) + (ym + yp)) + (zm + zp);
     const double c6 = 6.0 * c;

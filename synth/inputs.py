@@ -45,6 +45,15 @@ def random_state(shape, seed: int, lo_u=0.0, hi_u=1.0, lo_v=0.0, hi_v=1.0):
     return u, v
 
 
+def subnormal_field(shape, seed: int, m_max: int = 1 << 20):
+    """A float64 array of `shape` holding m 2^-1074 with m uniform in
+    [0, m_max): subnormal values (and zeros), as in the decayed tails of a
+    field."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(0, m_max, size=shape, dtype=np.uint64)
+    return m.view(np.float64)
+
+
 def batch_sweep(n_sims: int = 256, seed: int = DEFAULT_SEED,
                 sides=tuple(range(32, 193, 16)), f_range=(0.01, 0.06),
                 k_range=(0.04, 0.07)):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from synth import random_state, workload
+from synth import random_state, subnormal_field, workload
 from tests.gpu_util import max_abs, require_gpu, window_from_device
 
 pytestmark = pytest.mark.gpu
@@ -82,6 +82,38 @@ def test_noise_config_bitwise(torch):
             s.step(40)
             u, v = s.read()
         assert np.array_equal(u, ue) and np.array_equal(v, ve), (noise, max_abs(u, ue))
+
+
+def _bits_equal(a, b):
+    return np.array_equal(np.ascontiguousarray(a).view(np.uint64), np.ascontiguousarray(b).view(np.uint64))
+
+
+@pytest.mark.parametrize("Dv,dt", [(0.5, 1.0), (1.0, 0.9)])
+def test_fp64_subnormal_states_bitwise(torch, Dv, dt):
+    """FP64 from states whose v is subnormal (m 2^-1074, m < 2^20, the decayed
+    tails of a field), with u = 0 and with u random, and from a state whose u
+    is subnormal too, in the single-step kernel and the blocked kernel with one
+    and three fused steps, bit for bit against the oracle. About one in twelve
+    such Laplacian numerators is an odd multiple of 3 2^-1074, whose quotient
+    by 6 is a tie of the subnormal grid that only the true division rounds to
+    even (Eq. 3 divides by 6)."""
+    from paper_2309_10292_amd import gs
+    shape = (12, 20, 40)
+    n = 7
+    p = dict(Du=0.2, Dv=Dv, F=0.02, k=0.048, dt=dt)
+    tiles = [(1, 1)] + [(t, T) for t in gs.tblock_tiles() for T in (1, 3) if T <= gs.max_tblock(t, "f64")]
+    v0 = subnormal_field(shape, seed=int(Dv * 10))
+    u_rand, _ = random_state(shape, seed=5, lo_u=0.2, hi_u=1.0)
+    for case, u0 in (("u=0", np.zeros(shape)), ("u random", u_rand),
+                     ("u subnormal", subnormal_field(shape, seed=99))):
+        ue, ve = O.run(u0, v0, n, **p)
+        assert np.count_nonzero(ve) > 0  # the tails have not all flushed to zero
+        for tile, T in tiles:
+            with _sim(shape, u0=u0, v0=v0, tile=tile, tblock=T, **p) as s:
+                s.step(n)
+                u, v = s.read()
+            assert _bits_equal(u, ue) and _bits_equal(v, ve), \
+                f"{case} Dv={Dv} tile={tile} T={T}: {np.count_nonzero(u != ue)} u, {np.count_nonzero(v != ve)} v cells differ"
 
 
 def test_resume_bitwise(torch):
@@ -192,6 +224,26 @@ def test_reduced_precision_within_bars(torch, small_ref):
             u, v = s.read()
         err = max(max_abs(u, small_ref[0]), max_abs(v, small_ref[1]))
         print(f"{storage}: max-abs {err:.3e}")
+        assert err <= bar, (storage, err)
+
+
+def test_reduced_precision_with_noise_l64(torch):
+    """FP32 / FP16 / BF16 storage with the noise term on (n = 1e-3, Philox
+    keyed as in FP64), L=64 cube state, 100 steps, against the FP64 oracle.
+    The storage types round the noise like every other update: FP32 keeps it
+    to about 1e-7 of u near 1, FP16 to half of 2^-10 and BF16 to half of 2^-7,
+    so the bars are those of the noise-free L=64 run."""
+    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}
+    p = dict(workload("small_l64"), noise=1e-3, seed=77)
+    u0, v0 = O.init_cube(L=64)
+    ue, ve = O.run(u0, v0, p["steps"], **p)
+    kw = {k: p[k] for k in ("Du", "Dv", "F", "k", "dt", "noise", "seed")}
+    for storage, bar in bars.items():
+        with _sim((64, 64, 64), storage=storage, **kw) as s:
+            s.step(p["steps"])
+            u, v = s.read()
+        err = max(max_abs(u, ue), max_abs(v, ve))
+        print(f"{storage} with noise: max-abs {err:.3e}")
         assert err <= bar, (storage, err)
 
 
