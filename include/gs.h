@@ -165,6 +165,17 @@ size_t gs_sqdiff_workspace_bytes(void);
 gs_status gs_sqdiff(const void *a, const void *b, size_t n, int32_t storage, void *workspace, void *hip_stream,
                     double *out);
 
+/* gs_sqdiff without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, kernel and result (bit for bit) as gs_sqdiff.
+ * The partial sums live in a static device array of the library (4 KiB per
+ * GPU, held until the process ends), found on first use on each device; the
+ * call allocates nothing. n <= 2^40 (GS_ERR_UNSUPPORTED beyond). Calls that
+ * overlap on one GPU (several host threads, or streams of one device) share
+ * that array and race: serialise them. Synchronising. */
+gs_status gs_sqdiff_noalloc(const void *a, const void *b, size_t n, int32_t storage, void *hip_stream,
+                            double *out);
+
 /* Waits for all work enqueued by this handle. */
 gs_status gs_sync(gs_sim *s);
 

@@ -24,7 +24,7 @@ LIB = os.path.join(LIBDIR, "libgs.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["gs_step.hip", "gs_tblock.hip", "gs_aux.hip", "gs_surrogate.hip", "gs_api.cpp", "gs_batch.cpp",
-           "gs_surrogate_api.cpp", "gs_tunecache.cpp"]
+           "gs_surrogate_api.cpp", "gs_tunecache.cpp", "gs_noalloc.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -113,6 +113,7 @@ SIGNATURES = [
     ("gs_batch_fill_cube", _I32, [_SIM, _I32, _I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double]),
     ("gs_sqdiff_workspace_bytes", _SZ, []),
     ("gs_sqdiff", _I32, [_VP, _VP, _SZ, _I32, _VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("gs_sqdiff_noalloc", _I32, [_VP, _VP, _SZ, _I32, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("gs_laplacian7", _I32, [_VP, _VP, _I32, _I32, _I32, _VP]),
     ("gs_copy", _I32, [_VP, _VP, _SZ, _VP]),
 ]
@@ -425,6 +426,18 @@ def sqdiff(a, b, stream=None):
     out = ctypes.c_double()
     check(load().gs_sqdiff(a.data_ptr(), b.data_ptr(), a.numel(), storage, _sqdiff_ws[dev].data_ptr(),
                            _stream_handle(stream), ctypes.byref(out)))
+    return out.value
+
+
+def sqdiff_noalloc(a, b, stream=None):
+    """As sqdiff, through gs_sqdiff_noalloc (the library's static scratch; no workspace)."""
+    import torch
+    assert a.is_cuda and b.is_cuda and a.dtype == b.dtype and a.numel() == b.numel()
+    assert a.is_contiguous() and b.is_contiguous()
+    storage = {torch.float64: 0, torch.float32: 1, torch.bfloat16: 2, torch.float16: 3}[a.dtype]
+    out = ctypes.c_double()
+    check(load().gs_sqdiff_noalloc(a.data_ptr(), b.data_ptr(), a.numel(), storage, _stream_handle(stream),
+                                   ctypes.byref(out)))
     return out.value
 
 
