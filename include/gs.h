@@ -340,6 +340,31 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
 /* One Adam step with the last gradient (bias-corrected moments). */
 gs_status gs_surrogate_adam(gs_surrogate *s, float lr, float beta1, float beta2, float eps);
 
+/* Inspection of the last forward pass (gs_surrogate_predict or
+ * gs_surrogate_loss_grad) and of the last backward pass, for tests: copies
+ * one workspace tensor, as stored, to `host` (at least the bytes given;
+ * rows = samples of that pass times nx*ny*nz, sample-major, x fastest):
+ *   GS_SURR_INPUT (layer 0)   the packed network input, BF16, 8 channels per
+ *                             row: (u_hi, v_hi, f, k, u_lo, v_lo, 0, 0), u and
+ *                             v as the BF16 pairs that share one weight;
+ *   GS_SURR_PRE (layer 0..2)  pre-activation z = conv + bias, BF16, 32 channels;
+ *   GS_SURR_ACT (layer 0..2)  GELU of the FP32 pre-activation, BF16, 32 channels;
+ *   GS_SURR_PRED (layer 3)    the FP32 prediction u then v (2 * rows floats);
+ *                             loss_grad's forward pass only (predict writes the
+ *                             caller's outputs);
+ *   GS_SURR_DOUT (layer 3)    dloss/dprediction, BF16, 8 channels (u, v, 0...);
+ *   GS_SURR_DPRE (layer 0..2) dloss/dz of that layer, BF16, 32 channels.
+ * Synchronising. GS_ERR_STATE when the pass has not run. */
+typedef enum gs_surr_tensor {
+    GS_SURR_INPUT = 0,
+    GS_SURR_PRE = 1,
+    GS_SURR_ACT = 2,
+    GS_SURR_PRED = 3,
+    GS_SURR_DOUT = 4,
+    GS_SURR_DPRE = 5
+} gs_surr_tensor;
+gs_status gs_surrogate_read_tensor(gs_surrogate *s, int32_t tensor, int32_t layer, void *host, size_t host_bytes);
+
 gs_status gs_surrogate_destroy(gs_surrogate *s);
 
 /* ------------------------------------------------------------------ */

@@ -49,6 +49,26 @@ def conv3d(a: np.ndarray, W: np.ndarray, b: np.ndarray | None = None) -> np.ndar
     return out
 
 
+def conv3d_input_grad(g: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Gradient of sum(g * conv3d(a, W)) with respect to a, for g of shape
+    (C_out, Z, Y, X): the transposed convolution. Output position p receives
+    W[o, i, d] g[o] from every output q whose offset-d neighbour is p, i.e.
+    q = p - (d - 1)."""
+    out = np.zeros((W.shape[1],) + g.shape[1:], dtype=np.float64)
+    for dz, dy, dx in offsets():
+        out += shifted(np.einsum("oi,ozyx->izyx", W[:, :, dz, dy, dx], g), 2 - dz, 2 - dy, 2 - dx)
+    return out
+
+
+def conv3d_weight_grad(g: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """Gradient of sum(g * conv3d(a, W)) with respect to W: for every offset
+    d, the correlation of the output gradient with the shifted input."""
+    gW = np.zeros((g.shape[0], a.shape[0], 3, 3, 3), dtype=np.float64)
+    for dz, dy, dx in offsets():
+        gW[:, :, dz, dy, dx] = np.einsum("ozyx,izyx->oi", g, shifted(a, dz, dy, dx))
+    return gW
+
+
 def gelu(z):
     return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
 

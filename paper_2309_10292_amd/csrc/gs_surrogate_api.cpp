@@ -29,7 +29,7 @@ int nchunks(int cins) { return (27 * cins + 31) / 32; }
 size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
-    size_t x0, z[3], a[3], pu, pv, dzA, dzB, dz4, par, grad, m, v, wf[4], wd[4], wpart, cpart, lpart, fk, total;
+    size_t x0, z[3], a[3], pu, pv, dz[3], dz4, par, grad, m, v, wf[4], wd[4], wpart, cpart, lpart, fk, total;
 };
 
 Layout layout(size_t cells, int B)
@@ -49,8 +49,8 @@ Layout layout(size_t cells, int B)
     }
     L.pu = take(rows * 4);
     L.pv = take(rows * 4);
-    L.dzA = take(rows * 32 * 2);
-    L.dzB = take(rows * 32 * 2);
+    // dz[l]: gradient of the loss with respect to layer l's pre-activation
+    for (int i = 0; i < 3; ++i) L.dz[i] = take(rows * 32 * 2);
     L.dz4 = take(rows * 8 * 2);
     L.par = take(GS_SURR_NPARAMS * 4);
     L.grad = take(GS_SURR_NPARAMS * 4);
@@ -89,6 +89,8 @@ struct gs_surrogate {
     hipStream_t stream;
     int adam_t;
     int last_batch; // samples of the last loss_grad (gradient present when > 0)
+    int last_fwd;   // samples of the last forward pass (predict or loss_grad)
+    bool last_fwd_loss; // the last forward pass was loss_grad's (prediction and data gradients match it)
 };
 
 namespace {
@@ -220,6 +222,8 @@ gs_status gs_surrogate_init(int32_t nx, int32_t ny, int32_t nz, int32_t max_batc
     s->stream = (hipStream_t)hip_stream;
     s->adam_t = 0;
     s->last_batch = 0;
+    s->last_fwd = 0;
+    s->last_fwd_loss = false;
     st = gs_surrogate_set_params(s, params);
     if (st != GS_OK) {
         s->magic = 0;
@@ -267,7 +271,10 @@ gs_status gs_surrogate_predict(gs_surrogate *s, int32_t nsamp, int32_t io_storag
     if (u_out == u || v_out == v || u_out == v || v_out == u) return fail(GS_ERR_INVALID_ARG, "outputs must not alias inputs");
     if ((st = upload_fk(s, nsamp, F, k)) != GS_OK) return st;
     hipError_t e = forward(s, nsamp, io_storage == GS_F64, u, v, u_out, v_out);
-    return e == hipSuccess ? GS_OK : hip_fail(e, "surrogate forward");
+    if (e != hipSuccess) return hip_fail(e, "surrogate forward");
+    s->last_fwd = nsamp;
+    s->last_fwd_loss = false; // the stored data gradients no longer match the activations
+    return GS_OK;
 }
 
 gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u, const float *v, const float *u_target,
@@ -295,8 +302,6 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
                                  at<uint16_t>(s, s->L.a[2])};
     const uint16_t *dz = dz4;
     int couts = 8;
-    uint16_t *bufs[2] = {at<uint16_t>(s, s->L.dzA), at<uint16_t>(s, s->L.dzB)};
-    int which = 0;
     for (int l = 3; l >= 0 && e == hipSuccess; --l) {
         WgradArgs w = {};
         w.geo = s->geo;
@@ -318,10 +323,9 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
         a.in = dz;
         a.wpack = at<uint16_t>(s, s->L.wd[l]);
         a.zprev = at<uint16_t>(s, s->L.z[l - 1]);
-        a.aout = bufs[which];
+        a.aout = at<uint16_t>(s, s->L.dz[l - 1]);
         e = launch_conv(couts, 2, MODE_DGRAD, 0, a, s->stream);
-        dz = bufs[which];
-        which ^= 1;
+        dz = a.aout;
         couts = 32;
     }
     std::vector<double> lp(loss_blocks());
@@ -335,6 +339,8 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
     for (double x : lp) sum += x;
     if (loss) *loss = sum / n_terms;
     s->last_batch = nsamp;
+    s->last_fwd = nsamp;
+    s->last_fwd_loss = true;
     return GS_OK;
 }
 
@@ -351,6 +357,54 @@ gs_status gs_surrogate_adam(gs_surrogate *s, float lr, float beta1, float beta2,
                                        at<float>(s, s->L.v), GS_SURR_NPARAMS, lr, beta1, beta2, eps, c1, c2, s->stream);
     if (e == hipSuccess) e = repack_all(s);
     return e == hipSuccess ? GS_OK : hip_fail(e, "Adam step");
+}
+
+gs_status gs_surrogate_read_tensor(gs_surrogate *s, int32_t tensor, int32_t layer, void *host, size_t host_bytes)
+{
+    gs_status st = scheck(s);
+    if (st != GS_OK) return st;
+    if (!host) return fail(GS_ERR_INVALID_ARG, "host is NULL");
+    const size_t rows = (size_t)s->last_fwd * s->geo.ncell;
+    size_t off = 0, bytes = 0;
+    switch (tensor) {
+    case GS_SURR_INPUT:
+        if (layer != 0) return fail(GS_ERR_INVALID_ARG, "the input has layer 0 only");
+        off = s->L.x0, bytes = rows * 8 * 2;
+        break;
+    case GS_SURR_PRE:
+    case GS_SURR_ACT:
+        if (layer < 0 || layer > 2) return fail(GS_ERR_INVALID_ARG, "hidden layer %d outside [0, 2]", layer);
+        off = tensor == GS_SURR_PRE ? s->L.z[layer] : s->L.a[layer], bytes = rows * 32 * 2;
+        break;
+    case GS_SURR_PRED:
+        if (layer != 3) return fail(GS_ERR_INVALID_ARG, "the prediction is layer 3's");
+        if (!s->last_fwd_loss) return fail(GS_ERR_STATE, "no prediction kept: call gs_surrogate_loss_grad first");
+        off = s->L.pu, bytes = rows * 4;
+        break;
+    case GS_SURR_DOUT:
+        if (layer != 3) return fail(GS_ERR_INVALID_ARG, "the output gradient is layer 3's");
+        off = s->L.dz4, bytes = rows * 8 * 2;
+        break;
+    case GS_SURR_DPRE:
+        if (layer < 0 || layer > 2) return fail(GS_ERR_INVALID_ARG, "hidden layer %d outside [0, 2]", layer);
+        off = s->L.dz[layer], bytes = rows * 32 * 2;
+        break;
+    default:
+        return fail(GS_ERR_INVALID_ARG, "unknown tensor %d", tensor);
+    }
+    if ((tensor == GS_SURR_DOUT || tensor == GS_SURR_DPRE) && !s->last_fwd_loss)
+        return fail(GS_ERR_STATE, "no backward pass since the last forward pass");
+    if (rows == 0) return fail(GS_ERR_STATE, "no forward pass yet");
+    if (tensor == GS_SURR_PRED) {
+        if (host_bytes < 2 * bytes) return fail(GS_ERR_INVALID_ARG, "host holds %zu bytes, needs %zu", host_bytes, 2 * bytes);
+    } else if (host_bytes < bytes) {
+        return fail(GS_ERR_INVALID_ARG, "host holds %zu bytes, needs %zu", host_bytes, bytes);
+    }
+    hipError_t e = hipMemcpyAsync(host, s->ws + off, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && tensor == GS_SURR_PRED)
+        e = hipMemcpyAsync((char *)host + bytes, s->ws + s->L.pv, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    return e == hipSuccess ? GS_OK : hip_fail(e, "surrogate tensor read");
 }
 
 gs_status gs_surrogate_destroy(gs_surrogate *s)

@@ -107,6 +107,7 @@ SIGNATURES = [
     ("gs_surrogate_loss_grad", _I32, [_SIM, _I32, _VP, _VP, _VP, _VP, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("gs_surrogate_adam", _I32, [_SIM, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    ("gs_surrogate_read_tensor", _I32, [_SIM, _I32, _I32, ctypes.c_void_p, _SZ]),
     ("gs_surrogate_destroy", _I32, [_SIM]),
     ("gs_set_step", _I32, [_SIM, ctypes.c_uint64]),
     ("gs_fill_cube", _I32, [_SIM, _I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_double]),
@@ -182,6 +183,14 @@ def max_tblock(tile: int, storage="f64", batch: bool = False) -> int:
     if L.gs_tile_info(int(tile), st, 1, None, None, ctypes.byref(mt)) != GS_OK:
         return 0
     return int(mt.value)
+
+
+def tile_info(tile: int, storage="f64", tblock: int = 1):
+    """Output tile (tx cells, ty rows) of `tile` for a storage type and depth."""
+    st = DTYPES[storage] if isinstance(storage, str) else int(storage)
+    tx, ty = ctypes.c_int32(), ctypes.c_int32()
+    check(load().gs_tile_info(int(tile), st, int(tblock), ctypes.byref(tx), ctypes.byref(ty), None))
+    return tx.value, ty.value
 
 
 def tblock_tiles():

@@ -1,11 +1,26 @@
 """The surrogate network on the GPU (MFMA BF16 kernels) against the FP64
 network oracle, its training, and the stencil-fallback controller.
 
-Tolerances: activations and weights are BF16 (8 significant bits, relative
-rounding 2^-9 per value) with FP32 accumulation; over four layers the
-relative error of the network's output correction is expected near 1e-2,
-so outputs are compared with relative L2 error <= 3e-2 and gradients with
-relative L2 error <= 6e-2 and cosine >= 0.998 per layer."""
+Layer by layer (test_layers_elementwise_full_path_shapes), every kernel is
+compared element by element with the oracle fed the GPU's own BF16 inputs
+(read back through gs_surrogate_read_tensor), under a per-element bound
+|gpu - ref| <= rtol |ref| + atol derived from the kernel's arithmetic:
+  - BF16 storage of a result: unit roundoff 2^-8 (rtol);
+  - FP32 accumulation on the matrix cores: each v_mfma_f32_16x16x32_bf16
+    adds 32 exact BF16 products to the accumulator, taken as at most 32 FP32
+    roundings, so a chain of m instructions errs by at most 32 m 2^-24 S, where
+    S is the same sum over absolute values (computed by the oracle);
+  - the GELU kernels' erf (Abramowitz and Stegun 7.1.26 evaluated in FP32):
+    at most 1e-6 absolute;
+  - weight and bias gradients: per-workgroup FP32 partials (the chain is the
+    workgroup's MFMAs or adds), folded in FP64, rounded once to FP32.
+The shapes (2 samples of 48 x 10 x 40) cover three x-patches, a partial
+y-patch, ten convolution z-chunks and three weight-gradient z-chunks.
+
+End to end (forward, loss and gradients from the original inputs), the
+relative L2 errors come from BF16 rounding through four layers and are
+bounded by norm bars set near the measured values (forward 6-8e-3, gradients
+2-3e-3)."""
 import numpy as np
 import pytest
 
@@ -70,7 +85,7 @@ def test_forward_matches_oracle(torch):
         got = np.concatenate([du_g.ravel(), dv_g.ravel()])
         rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"sample {i}: relative L2 of the correction {rel:.3e}, |ref| max {np.max(np.abs(ref)):.3e}")
-        assert rel <= 3e-2, rel
+        assert rel <= 1.5e-2, rel
     assert np.max(np.abs(pu32.cpu().numpy() - pu)) <= 1e-6 + 1e-2 * np.max(np.abs(pu - u))
 
 
@@ -97,7 +112,7 @@ def test_gradients_match_oracle(torch):
                         f32(vt[i])))
     loss_e, grads = S.loss_and_grads(params, samples)
     print(f"loss gpu {loss:.6e} oracle {loss_e:.6e}")
-    assert abs(loss - loss_e) <= 3e-2 * loss_e
+    assert abs(loss - loss_e) <= 2e-3 * loss_e
     ge = S.flatten(grads)
     o = 0
     for l, (W, b) in enumerate(grads):
@@ -108,8 +123,132 @@ def test_gradients_match_oracle(torch):
             rel = np.linalg.norm(a - e) / np.linalg.norm(e)
             cos = float(a @ e / (np.linalg.norm(a) * np.linalg.norm(e)))
             print(f"layer {l} {'W' if arr is W else 'b'}: rel {rel:.3e} cos {cos:.6f}")
-            assert rel <= 6e-2 and cos >= 0.998, (l, rel, cos)
+            assert rel <= 1e-2 and cos >= 0.9999, (l, rel, cos)
     assert o == ge.size
+
+
+U = 2.0 ** -24   # FP32 unit roundoff
+B = 2.0 ** -8    # BF16 unit roundoff
+ERF = 1e-6       # erf of the GELU kernels, absolute
+
+
+def _check(name, got, ref, bound):
+    err = np.abs(got - ref)
+    worst = float(np.max(err / bound))
+    mag = np.abs(ref)
+    tight = float(np.median(bound[mag > 0] / mag[mag > 0])) if np.any(mag > 0) else float("nan")
+    print(f"{name}: max |gpu - ref| {float(np.max(err)):.3e}, max |ref| {float(np.max(mag)):.3e}, "
+          f"worst error / bound {worst:.3f}, median bound / |ref| {tight:.2e}")
+    assert worst <= 1.0, (name, worst)
+
+
+def test_layers_elementwise_full_path_shapes(torch):
+    """Every layer's forward, data-gradient, weight- and bias-gradient kernel
+    element by element against the oracle on the GPU's own BF16 inputs."""
+    from paper_2309_10292_amd.surrogate import Surrogate
+    nz, ny, nx, n = 40, 10, 48, 2
+    shape = (nz, ny, nx)
+    p32 = _params(13)
+    u, v = _fields(shape, n, 14)
+    rng = np.random.default_rng(15)
+    ut = u + 0.02 * rng.normal(size=u.shape)
+    vt = v + 0.02 * rng.normal(size=v.shape)
+    F, k = np.array([0.025, 0.05]), np.array([0.045, 0.065])
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    with Surrogate(nx, ny, nz, max_batch=n, params=p32) as m:
+        T = lambda a: torch.from_numpy(a.astype(np.float32)).cuda().contiguous()
+        loss, g = m.loss_grad(T(u), T(v), T(ut), T(vt), F, k, want_grad=True)
+        X = m.read_tensor(m.INPUT, 0, n).astype(np.float64)
+        Z = [m.read_tensor(m.PRE, l, n).astype(np.float64) for l in range(3)]
+        A = [m.read_tensor(m.ACT, l, n).astype(np.float64) for l in range(3)]
+        P = m.read_tensor(m.PRED, 3, n).astype(np.float64)
+        D4 = m.read_tensor(m.DOUT, 3, n).astype(np.float64)
+        DZ = [m.read_tensor(m.DPRE, l, n).astype(np.float64) for l in range(3)]
+    params = S.unflatten(p32.astype(np.float64))
+    Wb = [bf16_round(W) for W, _ in params]        # the kernels' BF16 weights
+    bb = [b for _, b in params]                    # biases stay FP32
+    cl = lambda a: np.moveaxis(a, -1, 0)           # (z, y, x, c) -> (c, z, y, x)
+    n_terms = 2 * n * nz * ny * nx
+    # chain lengths: forward / data-gradient MFMAs per output, weight-gradient
+    # MFMAs per workgroup partial, bias-gradient FP32 adds per partial
+    items = (nx // 16) * ((ny + 3) // 4) * ((nz + 15) // 16) * n
+    per_wg = -(-items // 512)
+    gam = lambda nch: 32 * nch * U
+    gam_w = 32 * (per_wg * 16 * 2) * U
+    gam_b = (per_wg * 16 * 4 + 16 + 1) * U
+    gW_all = S.unflatten(g.astype(np.float64))
+    sums_W = [np.zeros_like(W) for W in Wb]
+    sums_b = [np.zeros_like(b) for b in bb]
+    abs_W = [np.zeros_like(W) for W in Wb]
+    abs_b = [np.zeros_like(b) for b in bb]
+    for i in range(n):
+        x = cl(X[i])
+        assert np.all(x[6:] == 0.0)
+        a_in = np.stack([x[0] + x[4], x[1] + x[5], x[2], x[3]])          # u, v as hi + lo pairs
+        a_abs = np.stack([np.abs(x[0]) + np.abs(x[4]), np.abs(x[1]) + np.abs(x[5]), np.abs(x[2]), np.abs(x[3])])
+        assert np.max(np.abs(a_in[0] - f32(u[i]))) <= 2.0 ** -15 * np.max(np.abs(u[i]))
+        ins, ins_abs = [a_in], [a_abs]
+        # forward, hidden layers: z = conv + b, a = GELU
+        for l in range(3):
+            zr = S.conv3d(ins[-1], Wb[l], bb[l])
+            Sz = S.conv3d(ins_abs[-1], np.abs(Wb[l]), np.abs(bb[l]))
+            gz = gam(7 if l == 0 else 27) + U
+            _check(f"sample {i} layer {l} pre-activation", cl(Z[l][i]), zr, B * np.abs(zr) + (1 + B) * gz * Sz + 1e-30)
+            ar = S.gelu(zr)
+            _check(f"sample {i} layer {l} activation", cl(A[l][i]), ar,
+                   B * np.abs(ar) + (1 + B) * (1.13 * gz * Sz + (ERF + 2 * U) * (np.abs(zr) + gz * Sz)) + 1e-30)
+            ins.append(cl(A[l][i]))
+            ins_abs.append(np.abs(cl(A[l][i])))
+        # output layer: pred = input + conv + b in FP32
+        cr = S.conv3d(ins[3], Wb[3], bb[3])
+        Sc = S.conv3d(ins_abs[3], np.abs(Wb[3]), np.abs(bb[3]))
+        res = np.stack([f32(u[i]), f32(v[i])])
+        pr = res + cr
+        _check(f"sample {i} prediction", P[:, i], pr,
+               (1 + 2 * U) * gam(27) * Sc + U * np.abs(cr) * 1.01 + U * np.abs(pr) * 1.01 + 1e-30)
+        # output gradient 2 (pred - target) / n_terms, stored in BF16
+        d4 = cl(D4[i])
+        assert np.all(d4[2:] == 0.0)
+        tgt = np.stack([f32(ut[i]), f32(vt[i])])
+        dr = (2.0 / n_terms) * (P[:, i] - tgt)
+        _check(f"sample {i} output gradient", d4[:2], dr, (B + 4 * U) * np.abs(dr) * 1.01 + 1e-38)
+        # backward: layer l's output gradient -> its weight and bias gradients,
+        # and the data gradient of the layer below through GELU'
+        douts = [cl(DZ[0][i]), cl(DZ[1][i]), cl(DZ[2][i]), d4[:2]]
+        for l in range(3, -1, -1):
+            dl = douts[l]
+            sums_W[l] += S.conv3d_weight_grad(dl, ins[l])
+            abs_W[l] += S.conv3d_weight_grad(np.abs(dl), ins_abs[l])
+            sums_b[l] += dl.sum(axis=(1, 2, 3))
+            abs_b[l] += np.abs(dl).sum(axis=(1, 2, 3))
+            if l == 0:
+                break
+            gd = S.conv3d_input_grad(dl, Wb[l])
+            Sd = S.conv3d_input_grad(np.abs(dl), np.abs(Wb[l]))
+            zp = cl(Z[l - 1][i])
+            gg = S.gelu_grad(zp)
+            ref = gd * gg
+            acc = np.abs(gd) + gam(7 if l == 3 else 27) * Sd
+            _check(f"sample {i} data gradient below layer {l}", douts[l - 1], ref,
+                   (B + 2 * U) * acc * (np.abs(gg) + ERF) + acc * ERF + 1.13 * gam(7 if l == 3 else 27) * Sd + 1e-38)
+    for l in range(4):
+        gW, gb = gW_all[l]
+        _check(f"layer {l} weight gradient", gW, sums_W[l], gam_w * abs_W[l] + 2 * U * np.abs(sums_W[l]) + 1e-38)
+        _check(f"layer {l} bias gradient", gb, sums_b[l], gam_b * abs_b[l] + 2 * U * np.abs(sums_b[l]) + 1e-38)
+    # end to end against the oracle from the original inputs
+    samples = [(f32(u[i]), f32(v[i]), float(np.float32(F[i])), float(np.float32(k[i])), f32(ut[i]), f32(vt[i]))
+               for i in range(n)]
+    loss_e, grads = S.loss_and_grads(S.unflatten(bf16_round(p32)), samples)
+    print(f"loss gpu {loss:.6e} oracle {loss_e:.6e}")
+    # the larger last layer makes the correction, and its BF16 error, large
+    # against the residual: 4.2e-3 measured
+    assert abs(loss - loss_e) <= 1e-2 * loss_e
+    for l, (W, b) in enumerate(grads):
+        for name, a, e in (("W", gW_all[l][0], W), ("b", gW_all[l][1], b)):
+            rel = np.linalg.norm(a - e) / np.linalg.norm(e)
+            cos = float(a.ravel() @ e.ravel() / (np.linalg.norm(a) * np.linalg.norm(e)))
+            print(f"end to end layer {l} {name}: rel {rel:.3e} cos {cos:.6f}")
+            assert rel <= 1e-2 and cos >= 0.9999, (l, name, rel, cos)
 
 
 def test_training_reduces_loss_and_controller(torch):
@@ -180,6 +319,10 @@ def test_trained_surrogate_gain_l128(torch):
     error of the network and of persistence (no change over 16 steps)
     against the FP64 stencil, the controller's fallbacks with the 1e-3 check
     every 4th jump, and the time of one jump against 16 stencil steps. It
+    also times the controlled run (surrogate jumps, checks, fallbacks) against
+    the plain stencil over the same 128 steps: the net gain of the learned
+    part at the 1e-3 tolerance. The check bounds the error of the checked jump
+    only; the window's end is compared with the plain stencil as well. It
     asserts only what the measurement must show regardless of speed: over
     the four trajectories the network predicts the 16-step change clearly
     better than persistence (a quiescent trajectory alone can sit below the
@@ -230,15 +373,21 @@ def test_trained_surrogate_gain_l128(torch):
                 ms_jump = timed(lambda: m.predict(u0, v0, b["F"], b["k"], pu, pv), 10)
                 ms_stencil = timed(lambda: s.step(JUMP), 10)
             with start(b) as s, start(b) as ref:
+                torch.cuda.synchronize()
                 r = run_controlled(m, s, b["F"], b["k"], jumps=8, check_every=4, tol=1e-3)
+                t0 = time.perf_counter()
                 ref.step(8 * JUMP)
+                torch.cuda.synchronize()
+                stencil_s = time.perf_counter() - t0
                 uc, vc, stc = s.current()
                 ur, vr, str_ = ref.current()
                 assert stc == str_ == warm + 8 * JUMP
                 end = rms(uc, ur, vc, vr)
             run = dict(F=b["F"], k=b["k"], one_jump_rms_net=net, one_jump_rms_persistence=pers,
                        ms_surrogate_jump=ms_jump, ms_stencil_16_steps=ms_stencil, speed_gain=ms_stencil / ms_jump,
-                       checks=r["checks"], fallbacks=r["fallbacks"], rms_at_checks=r["rms"], rms_end_vs_stencil=end)
+                       checks=r["checks"], fallbacks=r["fallbacks"], rms_at_checks=r["rms"], rms_end_vs_stencil=end,
+                       controlled_seconds=r["seconds"], stencil_seconds=stencil_s,
+                       net_gain_vs_stencil=stencil_s / r["seconds"])
             report["runs"].append(run)
             print(json.dumps(run))
             if r["fallbacks"] == r["checks"]:

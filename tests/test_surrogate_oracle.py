@@ -37,6 +37,22 @@ def test_conv_matches_torch_circular():
     assert np.max(np.abs(S.conv3d(a, W, b) - ref)) < 1e-12
 
 
+def test_conv_gradients_match_torch_autograd():
+    """The data-gradient (transposed) convolution and the weight gradient of
+    one circular convolution against torch's autograd in FP64."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(5, 4, 6, 7))
+    W = rng.normal(size=(3, 5, 3, 3, 3))
+    g = rng.normal(size=(3, 4, 6, 7))
+    at = torch.from_numpy(a)[None].requires_grad_(True)
+    Wt = torch.from_numpy(W).requires_grad_(True)
+    out = torch.nn.functional.conv3d(torch.nn.functional.pad(at, (1, 1, 1, 1, 1, 1), mode="circular"), Wt)
+    (out * torch.from_numpy(g)[None]).sum().backward()
+    assert np.max(np.abs(S.conv3d_input_grad(g, W) - at.grad[0].numpy())) < 1e-11
+    assert np.max(np.abs(S.conv3d_weight_grad(g, a) - Wt.grad.numpy())) < 1e-11
+
+
 def test_gelu_closed_form():
     z = np.linspace(-6, 6, 101)
     exp = np.array([0.5 * x * (1 + math.erf(x / math.sqrt(2))) for x in z])
