@@ -225,27 +225,27 @@ gs_status check(gs_sim *s)
 }
 
 // Library choice of the launch configuration before any tuning (from the
-// MI355X autotuner sweeps at 512^3 and 1024^3): large grids use the
-// temporally blocked kernel: FP64 with three fused steps (64 x 22 tiles, 512
-// lanes), FP32 with two in the same shape (the compensated Laplacian makes
-// deeper fusion arithmetic-bound), FP16 with one step in 768-lane
-// workgroups, BF16 with one step in 256-lane workgroups when noise is on;
-// BF16 without noise keeps the single-step kernel, and so do small grids.
+// MI355X autotuner sweeps at 512^3 with noise and 1024^3 without): large
+// grids use the temporally blocked kernel. FP64 fuses three steps in the
+// 512-lane 64 x 22 tile. With noise, the other storage types fuse two steps
+// in the same tile (the Philox blocks of deeper fusion cost more than the
+// traffic they save); without noise FP32 fuses two steps and the 16-bit
+// types one in the 1024-lane tile. Small grids keep the single-step kernel.
 bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
 {
     if (!large_grid(p)) return 1;
-    if (p.storage == GS_F64 || p.storage == GS_F32) return gs::num_tiles() + 2;
-    if (p.storage == GS_F16) return gs::num_tiles() + 4;
-    if (p.storage == GS_BF16 && p.noise != 0.0) return gs::num_tiles() + 1;
-    return 1;
+    if (p.storage == GS_F64 || p.noise != 0.0) return gs::num_tiles() + 2;
+    return gs::num_tiles() + 5;
 }
 
 int default_tblock(const gs_params &p, int tile)
 {
     if (tile <= gs::num_tiles()) return 1;
-    const int T = p.storage == GS_F64 ? 3 : p.storage == GS_F32 ? 2 : 1;
+    int T = 1;
+    if (p.storage == GS_F64) T = 3;
+    else if (p.storage == GS_F32 || p.noise != 0.0) T = 2;
     const int mt = tile_max_tblock(tile, p.storage);
     return T < mt ? T : mt;
 }

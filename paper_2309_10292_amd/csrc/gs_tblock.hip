@@ -26,6 +26,7 @@
 // The noise of level k uses step index t + k - 1.
 #include "gs_device.hpp"
 #include "gs_launch.hpp"
+#include "gs_tblock_common.hpp"
 
 namespace gs {
 
@@ -68,76 +69,6 @@ template <typename S, int TXG, int TY, int T, int NT> struct TbGeom {
     static_assert(2 * FIELD * sizeof(C) <= 160 * 1024, "staged planes fit the LDS of a CU");
     static constexpr int row_base(int k) { return k * RY0 - k * (k - 1); }
 };
-
-template <typename S> struct NtStore;
-template <> struct NtStore<double> {
-    static __device__ __forceinline__ void put(double *p, const Vec<double, 4> &v)
-    {
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        d2 a = {v.e[0], v.e[1]}, b = {v.e[2], v.e[3]};
-        __builtin_nontemporal_store(a, reinterpret_cast<d2 *>(p));
-        __builtin_nontemporal_store(b, reinterpret_cast<d2 *>(p) + 1);
-    }
-};
-template <> struct NtStore<float> {
-    static __device__ __forceinline__ void put(float *p, const Vec<float, 4> &v)
-    {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        f4 a = {v.e[0], v.e[1], v.e[2], v.e[3]};
-        __builtin_nontemporal_store(a, reinterpret_cast<f4 *>(p));
-    }
-};
-template <> struct NtStore<bf16> {
-    static __device__ __forceinline__ void put(bf16 *p, const Vec<bf16, 4> &v)
-    {
-        typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        u2 a = {(unsigned)v.e[0].bits | ((unsigned)v.e[1].bits << 16), (unsigned)v.e[2].bits | ((unsigned)v.e[3].bits << 16)};
-        __builtin_nontemporal_store(a, reinterpret_cast<u2 *>(p));
-    }
-};
-template <> struct NtStore<f16> {
-    static __device__ __forceinline__ void put(f16 *p, const Vec<f16, 4> &v)
-    {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        h4 a = {v.e[0], v.e[1], v.e[2], v.e[3]};
-        __builtin_nontemporal_store(a, reinterpret_cast<h4 *>(p));
-    }
-};
-
-template <int P> struct Phase {
-    static constexpr int value = P;
-};
-template <bool F> struct Full {
-    static constexpr bool value = F;
-};
-// Slot of a plane whose offset from the first loop plane is p (any sign).
-__host__ __device__ constexpr int slot3(int p) { return ((p % 3) + 3) % 3; }
-
-// UNIT_DT: dt is exactly 1, so the products du dt and dv dt equal du and dv
-// (bitwise) and are skipped. nr is the noise term n r. FP64 follows the
-// definition's operation order; FP32 arithmetic takes the fused sequence
-// shared by every FP32 kernel.
-template <typename C, bool UNIT_DT, bool NOISE>
-__device__ __forceinline__ void cell_update(const StepArgs &a, C uc, C vc, C lu, C lv, C nr, C &uo, C &vo)
-{
-    if constexpr (sizeof(C) == 4) {
-        euler_f32<NOISE>(a.Du_f, a.Dv_f, a.F_f, a.FK_f, a.dt_f, uc, vc, lu, lv, nr, uo, vo);
-    } else {
-        const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
-        const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
-        const C uvv = uc * (vc * vc);
-        C du = (Du * lu - uvv) + F * ((C)1 - uc);
-        if constexpr (NOISE) du = du + nr;
-        const C dv = (Dv * lv + uvv) - FK * vc;
-        if constexpr (UNIT_DT) {
-            uo = uc + du;
-            vo = vc + dv;
-        } else {
-            uo = uc + du * dt;
-            vo = vc + dv * dt;
-        }
-    }
-}
 
 // One output tile [x0, x0 + 4 TXG) x [y0, y0 + TY) x [z0, ze) of a grid
 // (a.nx, a.ny, a.nz), T steps from (u, v) into (un, vn); t0 is the step index
