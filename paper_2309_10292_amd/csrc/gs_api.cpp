@@ -225,27 +225,35 @@ gs_status check(gs_sim *s)
 }
 
 // Library choice of the launch configuration before any tuning (from the
-// MI355X autotuner sweeps at 512^3 with noise and 1024^3 without): large
-// grids use the temporally blocked kernel. FP64 fuses three steps in the
-// 512-lane 64 x 22 tile. With noise, the other storage types fuse two steps
-// in the same tile (the Philox blocks of deeper fusion cost more than the
-// traffic they save); without noise FP32 fuses two steps and the 16-bit
-// types one in the 1024-lane tile. Small grids keep the single-step kernel.
-bool large_grid(const gs_params &p) { return (double)p.nx * p.ny * p.nz >= 64.0 * 1024 * 1024; }
+// MI355X autotuner sweeps at 64^3 .. 1024^3, with and without noise): the
+// temporally blocked kernel at every size. Large grids (>= 64 M cells): FP64
+// fuses three steps in the 512-lane 64 x 22 tile; with noise the other
+// storage types fuse two steps in the same tile (the Philox blocks of deeper
+// fusion cost more than the traffic they save); without noise FP32 fuses two
+// steps and the 16-bit types one in the 1024-lane tile. Smaller grids fuse
+// two steps: in 256-lane workgroups below 4 M cells (more workgroups for
+// 256 CUs), above that in the 768-lane tile for FP64 and the 512-lane one for
+// the others. The single-step kernel (tiles 1..4) runs when asked for.
+double grid_cells(const gs_params &p) { return (double)p.nx * p.ny * p.nz; }
+bool large_grid(const gs_params &p) { return grid_cells(p) >= 64.0 * 1024 * 1024; }
 
 int default_tile(const gs_params &p)
 {
-    if (!large_grid(p)) return 1;
-    if (p.storage == GS_F64 || p.noise != 0.0) return gs::num_tiles() + 2;
-    return gs::num_tiles() + 5;
+    const int tb = gs::num_tiles(); // tiles tb + 1 .. tb + 5 are the blocked shapes 1..5
+    if (grid_cells(p) < 4.0 * 1024 * 1024) return tb + 1;
+    if (!large_grid(p)) return p.storage == GS_F64 ? tb + 4 : tb + 2;
+    if (p.storage == GS_F64 || p.noise != 0.0) return tb + 2;
+    return tb + 5;
 }
 
 int default_tblock(const gs_params &p, int tile)
 {
     if (tile <= gs::num_tiles()) return 1;
-    int T = 1;
-    if (p.storage == GS_F64) T = 3;
-    else if (p.storage == GS_F32 || p.noise != 0.0) T = 2;
+    int T = 2;
+    if (large_grid(p)) {
+        if (p.storage == GS_F64) T = 3;
+        else if (p.storage != GS_F32 && p.noise == 0.0) T = 1;
+    }
     const int mt = tile_max_tblock(tile, p.storage);
     return T < mt ? T : mt;
 }
@@ -258,10 +266,11 @@ const int k_zchunks[] = {4, 8, 16, 32, 64, 128, 256, 512};
 // workgroups per CU) take ceil(nb / slots) rounds, so the sweep costs about
 // ceil(nb / slots) (zc + 2T) plane times; the partly filled last round costs
 // up to a fifth of the throughput at 512^3 with a fixed chunk. Chunks that
-// leave fewer than three rounds are slower than this predicts (every CU then
-// starts and drains its workgroups at once), so the cheapest chunk with at
-// least three rounds is taken (the larger one on ties), else the shortest
-// chunk. The single-step kernel keeps chunks of at most 32 planes (longer
+// leave fewer than three rounds are slower than this predicts on large grids
+// (every CU then starts and drains its workgroups at once), so the cheapest
+// chunk with at least three rounds (two below 64 M cells, where longer
+// chunks measured faster) is taken (the larger one on ties), else the
+// shortest chunk. The single-step kernel keeps chunks of at most 32 planes (longer
 // ones measured slower at 1024^3 although the estimate favours them).
 // Without the occupancy figures it falls back to fixed chunks.
 int default_zc(const gs_params &p, int tile, int tblock)
@@ -278,12 +287,13 @@ int default_zc(const gs_params &p, int tile, int tblock)
         const double slots = (double)cus * occ;
         const double tiles = (double)((p.nx + t.tx - 1) / t.tx) * (double)((p.ny + t.ty - 1) / t.ty);
         const int T = tb ? tblock : 1;
+        const double min_rounds = large_grid(p) ? 3.0 : 2.0;
         double best = 1e300;
         int bz = 0;
         for (int z : k_zchunks) {
             const int zc = z < p.nz ? z : p.nz;
             const double nb = tiles * (double)((p.nz + zc - 1) / zc);
-            if (nb < 3.0 * slots || (!tb && z > 32)) continue;
+            if (nb < min_rounds * slots || (!tb && z > 32)) continue;
             const double cost = std::ceil(nb / slots) * (double)(zc + 2 * T);
             if (cost <= best) {
                 best = cost;
