@@ -116,8 +116,10 @@ gs_status gs_tile_info(int32_t tile, int32_t storage, int32_t tblock, int32_t *t
                        int32_t *max_tblock);
 
 /* Binds four caller-owned device buffers of nx*ny*nz elements of the storage
- * type. (u0, v0) hold the state at step p->step0; (u1, v1) receive the next
- * level; the library ping-pongs between the pairs. `workspace` holds
+ * type. (u0, v0) hold the state at step p->step0; (u1, v1) are the second
+ * allocation of both fields that receives the next time level (the
+ * temporaries of Sec. 3.2, On-Node Parallelization); the library ping-pongs
+ * between the pairs. `workspace` holds
  * gs_workspace_bytes(p) bytes. If p->init_mode == GS_INIT_CUBE the init
  * kernel fills (u0, v0) on `hip_stream`. Does not allocate device memory.
  * On success *out is a new handle; on failure *out is NULL. */
@@ -131,7 +133,9 @@ gs_status gs_init(const gs_params *p, void *u0, void *v0, void *u1, void *v1,
 gs_status gs_step(gs_sim *s, int64_t n_steps);
 
 /* Synchronising. Copies the current u and/or v, widened to FP64, into host
- * arrays of nx*ny*nz doubles (NULL skips that field). */
+ * arrays of nx*ny*nz doubles (NULL skips that field): the state the paper's
+ * workflow hands to output and analysis (Sec. 3.4). x varies fastest:
+ * element x + nx*(y + ny*z). */
 gs_status gs_read(gs_sim *s, double *u_host, double *v_host);
 
 /* Synchronising. Replaces the current u and/or v by host FP64 arrays of
@@ -139,13 +143,17 @@ gs_status gs_read(gs_sim *s, double *u_host, double *v_host);
  * 16-bit type; nearest-even). NULL leaves that field unchanged. */
 gs_status gs_write(gs_sim *s, const double *u_host, const double *v_host);
 
-/* Zero-copy view: device pointers of the buffers holding the current state,
- * and the global step index of that state. Any output pointer may be NULL. */
+/* Zero-copy view: device pointers of the buffers holding the current state
+ * (which of the two allocations of Sec. 3.2 holds the newest time level),
+ * and the global step index of that state. Any output pointer may be NULL.
+ * The pointers stay owned by the caller; they change after each step. */
 gs_status gs_current(gs_sim *s, void **u_dev, void **v_dev, uint64_t *step);
 
-/* Synchronising. FP64 compensated sums (the mass sum(u + v) is
- * sum_u + sum_v), per-field min/max and the non-finite count of the current
- * state. Returns GS_ERR_NONFINITE (with *out filled) when nonfinite > 0. */
+/* Synchronising. Per-field min/max of the current state, as the paper's
+ * provenance record reports them for U and V at each output step
+ * (Listing 1), with FP64 compensated sums (the mass sum(u + v) is
+ * sum_u + sum_v) and the non-finite count. Returns GS_ERR_NONFINITE (with
+ * *out filled) when nonfinite > 0. */
 gs_status gs_diagnostics(gs_sim *s, gs_diag *out);
 
 /* Sets the global step index of the current state (the noise key of the
