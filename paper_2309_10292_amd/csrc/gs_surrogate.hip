@@ -74,7 +74,10 @@ __device__ __forceinline__ bf16x8 load8(const u16 *p)
 // with a one-cell ring (18 x 6 cells) sit in an LDS ring of three planes next
 // to the packed weights, so every input value is fetched from L2 once per
 // chunk instead of once per offset; the plane z+2 is loaded into registers
-// while plane z is computed.
+// while plane z is computed. Every MFMA operand is read from LDS: the ring is
+// stored channel group major so that a fragment read is 256 contiguous bytes
+// per 16 lanes (no bank conflicts), and the K loop keeps its reads a few
+// chunks ahead of the MFMAs that use them.
 constexpr int PX = 16, PY = 4;               // patch (x, y)
 constexpr int RX = PX + 2, RY = PY + 2;      // ring plane (x, y)
 constexpr int RCELLS = RX * RY;              // cells per ring plane
@@ -84,8 +87,16 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
 {
     constexpr int NCH = (27 * CIN + 31) / 32;
     constexpr int VPC = CIN / 8;              // 16-byte vectors per cell
-    constexpr int PLANE_V = RCELLS * VPC;     // 16-byte vectors per ring plane
-    constexpr int LOADS = (PLANE_V + 255) / 256;
+    // Ring layout: channel group major, cells contiguous within a group, so
+    // the 16 lanes of a channel group read 16 consecutive cells (256
+    // contiguous bytes, free of bank conflicts); each group's cells are padded
+    // to a multiple of 16 vectors (256 bytes).
+    constexpr int GCELLS = (RCELLS + 15) / 16 * 16;
+    constexpr int PLANE_V = GCELLS * VPC;     // 16-byte vectors per ring plane
+    constexpr int LOAD_V = RCELLS * VPC;      // vectors loaded per plane
+    constexpr int LOADS = (LOAD_V + 255) / 256;
+    // ring position of loaded vector v (cell v / VPC, channel group v % VPC)
+    auto ring_pos = [](int v) { return (v % VPC) * GCELLS + v / VPC; };
     __shared__ uint4 wl[NCH * NT * 64];
     __shared__ uint4 ring[3 * PLANE_V];
     const uint4 *wg = reinterpret_cast<const uint4 *>(a.wpack);
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
     for (int p = 0; p < 3; ++p) {
         const int z = z0 - 1 + p; // ring slot of plane z is (z mod 3)
         const int slot = ((z % 3) + 3) % 3;
-        for (int v = threadIdx.x; v < PLANE_V; v += 256) ring[slot * PLANE_V + v] = *ring_src(v, z);
+        for (int v = threadIdx.x; v < LOAD_V; v += 256) ring[slot * PLANE_V + ring_pos(v)] = *ring_src(v, z);
     }
     __syncthreads();
 
@@ -129,8 +140,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
         // an in-range vector (indices clamped) and only the LDS store is masked
         const bool more = z + 1 < ze;
         static_assert(LOADS <= 2, "a ring plane is at most two vectors per lane");
-        const uint4 pre0 = *ring_src(min((int)threadIdx.x, PLANE_V - 1), z + 2);
-        const uint4 pre1 = LOADS > 1 ? *ring_src(min((int)threadIdx.x + 256, PLANE_V - 1), z + 2) : pre0;
+        const uint4 pre0 = *ring_src(min((int)threadIdx.x, LOAD_V - 1), z + 2);
+        const uint4 pre1 = LOADS > 1 ? *ring_src(min((int)threadIdx.x + 256, LOAD_V - 1), z + 2) : pre0;
         f32x4 acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -138,24 +149,29 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
         // cells), so a lane's accumulators are 4 consecutive output channels
         // of one cell.
         if constexpr (CIN == 32) {
-            // K chunk c is offset d = c with all 32 input channels: one ring
-            // slot per dz, its nine (dy, dx) offsets unrolled.
-            // Rolled in the forward hidden layer, unrolled elsewhere (each
-            // measured the faster there).
-            constexpr int DZ_UNROLL = MODE == MODE_HIDDEN ? 1 : 3;
-#pragma unroll DZ_UNROLL
-            for (int dz = 0; dz < 3; ++dz) {
+            // K chunk c is offset d = c with all 32 input channels. The 27
+            // chunks are unrolled with the fragments of the next KD chunks in
+            // flight (a register ring), so each MFMA's LDS reads were issued
+            // KD chunks earlier.
+            constexpr int KD = 3;
+            bf16x8 avr[KD], wvr[KD][NT];
+            auto load = [&](int c, int sl) {
+                const int dz = c / 9, dy = (c / 3) % 3, dx = c % 3;
                 const uint4 *rs = ring + ((z + dz + 2) % 3) * PLANE_V; // slot of plane z + dz - 1
+                avr[sl] = __builtin_bit_cast(bf16x8, rs[quad * GCELLS + (wave + dy) * RX + col + dx]);
 #pragma unroll
-                for (int j = 0; j < 9; ++j) {
-                    const int dy = j / 3, dx = j % 3, c = 9 * dz + j;
-                    const bf16x8 av = __builtin_bit_cast(bf16x8, rs[((wave + dy) * RX + col + dx) * VPC + quad]);
+                for (int t = 0; t < NT; ++t) wvr[sl][t] = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+            };
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        const bf16x8 wv = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, av, acc[t], 0, 0, 0);
-                    }
-                }
+            for (int c = 0; c < KD; ++c) load(c, c);
+#pragma unroll
+            for (int c = 0; c < 27; ++c) {
+                const int sl = c % KD;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvr[sl][t], avr[sl], acc[t], 0, 0, 0);
+                if (c + KD < 27) load(c + KD, sl);
+                // keep the reads KD chunks ahead of their MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
         } else {
 #pragma unroll 9
@@ -167,7 +183,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
                     const int dz = d / 9, dy = (d / 3) % 3, dx = d % 3;
                     const int slot = (((z + dz - 1) % 3) + 3) % 3;
                     const int cell = (wave + dy) * RX + col + dx;
-                    av = __builtin_bit_cast(bf16x8, ring[slot * PLANE_V + cell * VPC + ci0 / 8]);
+                    av = __builtin_bit_cast(bf16x8, ring[slot * PLANE_V + (ci0 / 8) * GCELLS + cell]);
                 } else {
                     av = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
                 }
@@ -223,8 +239,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
         __syncthreads(); // every read of plane z-1's slot is done
         if (more) {
             const int slot = ((z + 2) % 3 + 3) % 3;
-            if ((int)threadIdx.x < PLANE_V) ring[slot * PLANE_V + threadIdx.x] = pre0;
-            if (LOADS > 1 && (int)threadIdx.x + 256 < PLANE_V) ring[slot * PLANE_V + threadIdx.x + 256] = pre1;
+            if ((int)threadIdx.x < LOAD_V) ring[slot * PLANE_V + ring_pos(threadIdx.x)] = pre0;
+            if (LOADS > 1 && (int)threadIdx.x + 256 < LOAD_V) ring[slot * PLANE_V + ring_pos(threadIdx.x + 256)] = pre1;
         }
         __syncthreads();
     }
