@@ -15,8 +15,9 @@ of GPU time is covered. `value` is the median block's rate; the spread of the
 blocks is reported beside it.
 
 Prints ONE JSON line: metric/value (G cell-updates/s), the roofline of the
-step kernel, the FP32/BF16/FP16 storage variants at the same workload (timed
-the same way, with their error against the FP64 state), and the CPU oracle
+step kernel, the FP32/BF16/FP16 storage variants and BF16 with u stored as
+1 - u ("bf16c") at the same workload (timed the same way, with their error
+against the FP64 state), and the CPU oracle
 timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -34,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-BYTES_PER_CELL = {"f64": 32, "f32": 16, "bf16": 8, "f16": 8}  # read u,v + write u,v once per step
+BYTES_PER_CELL = {"f64": 32, "f32": 16, "bf16": 8, "f16": 8, "bf16c": 8}  # read u,v + write u,v once per step
 # Vector issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at
 # 2.4 GHz = 39.3 T lane-instructions/s; FP64 add/mul/fma issue at that rate
 # (78.6 TFLOP/s counting an fma as two).
@@ -65,7 +66,7 @@ def alu_ops_per_cell_update(storage, noise):
 
 
 def kernel_name(cfg, storage, noise):
-    ctype = {"f64": "double", "f32": "float", "bf16": "bf16", "f16": "f16"}[storage]
+    ctype = {"f64": "double", "f32": "float", "bf16": "bf16", "f16": "f16", "bf16c": "bf16c"}[storage]
     tile = cfg["tile"]
     if tile in TB_LANES:
         return (f"stencil_tb<{ctype}, {cfg['tx'] // 4}, {cfg['ty']}, {cfg['tblock']}, {TB_LANES[tile]}, "
@@ -145,7 +146,7 @@ def parse(argv=None):
     ap.add_argument("--tblock", type=int, default=0, help="fused steps per sweep, 0 = library choice")
     ap.add_argument("--zchunk", type=int, default=0, help="planes per workgroup chunk, 0 = library choice")
     ap.add_argument("--tune", action="store_true", help="autotune the launch configuration first")
-    ap.add_argument("--variants", default="f32,bf16,f16", help="other storage types to time, or 'none'")
+    ap.add_argument("--variants", default="f32,bf16,f16,bf16c", help="other storage types to time, or 'none'")
     ap.add_argument("--blocks", type=int, default=0, help="timed blocks (0: at least 5, until 0.5 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="budget of the all-thread oracle sample")

@@ -46,8 +46,12 @@ typedef enum gs_status {
 /* Storage type of the fields in device memory. GS_F64 computes in FP64 and
  * reproduces the FP64 definition of the step bit for bit; the other types
  * compute in FP32 (Laplacian neighbour sum compensated) and round each stored
- * value to nearest-even. */
-typedef enum gs_dtype { GS_F64 = 0, GS_F32 = 1, GS_BF16 = 2, GS_F16 = 3 } gs_dtype;
+ * value to nearest-even. GS_BF16C is BF16 storage that keeps 1 - u in place
+ * of u (v as it is): where u is near 1, most of a Gray-Scott state, 1 - u is
+ * small and BF16 keeps eight significant bits of it, where plain BF16 steps
+ * u by 2^-8. Its u buffers hold 1 - u (gs_read, gs_write and gs_diagnostics
+ * convert; gs_current hands out the raw buffers); not for batched sweeps. */
+typedef enum gs_dtype { GS_F64 = 0, GS_F32 = 1, GS_BF16 = 2, GS_F16 = 3, GS_BF16C = 4 } gs_dtype;
 
 typedef enum gs_init_mode {
     GS_INIT_NONE = 0, /* the caller has filled u0, v0 (storage type) */

@@ -44,6 +44,7 @@ size_t storage_bytes(int32_t s)
     case GS_F32: return 4;
     case GS_BF16: return 2;
     case GS_F16: return 2;
+    case GS_BF16C: return 2;
     }
     return 0;
 }
@@ -118,7 +119,8 @@ float host_from_bf16(uint16_t b)
     return f;
 }
 
-gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, hipStream_t st)
+// field: 0 = u, 1 = v (GS_BF16C stores 1 - u).
+gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, hipStream_t st, int field)
 {
     const size_t es = storage_bytes(storage);
     if (storage == GS_F64) {
@@ -136,6 +138,12 @@ gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, h
     } else if (storage == GS_BF16) {
         const uint16_t *x = (const uint16_t *)stage.data();
         for (size_t i = 0; i < n; ++i) host[i] = host_from_bf16(x[i]);
+    } else if (storage == GS_BF16C) {
+        const uint16_t *x = (const uint16_t *)stage.data();
+        if (field == 0)
+            for (size_t i = 0; i < n; ++i) host[i] = 1.0 - (double)host_from_bf16(x[i]);
+        else
+            for (size_t i = 0; i < n; ++i) host[i] = host_from_bf16(x[i]);
     } else {
         const _Float16 *x = (const _Float16 *)stage.data();
         for (size_t i = 0; i < n; ++i) host[i] = (double)(float)x[i];
@@ -143,7 +151,7 @@ gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, h
     return GS_OK;
 }
 
-gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, hipStream_t st)
+gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, hipStream_t st, int field)
 {
     const size_t es = storage_bytes(storage);
     std::vector<unsigned char> stage;
@@ -156,6 +164,13 @@ gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, 
         } else if (storage == GS_BF16) {
             uint16_t *d = (uint16_t *)stage.data();
             for (size_t i = 0; i < n; ++i) d[i] = host_bf16((float)host[i]);
+        } else if (storage == GS_BF16C) {
+            // u: 1 - u formed in FP64, then rounded to FP32 and to BF16
+            uint16_t *d = (uint16_t *)stage.data();
+            if (field == 0)
+                for (size_t i = 0; i < n; ++i) d[i] = host_bf16((float)(1.0 - host[i]));
+            else
+                for (size_t i = 0; i < n; ++i) d[i] = host_bf16((float)host[i]);
         } else {
             _Float16 *d = (_Float16 *)stage.data();
             for (size_t i = 0; i < n; ++i) d[i] = (_Float16)(float)host[i];
@@ -489,7 +504,7 @@ gs_status gs_read(gs_sim *s, double *u_host, double *v_host)
     double *dst[2] = {u_host, v_host};
     for (int f = 0; f < 2; ++f) {
         if (!dst[f]) continue;
-        st = read_field(s->buf[s->parity][f], s->p.storage, s->n, dst[f], s->stream);
+        st = read_field(s->buf[s->parity][f], s->p.storage, s->n, dst[f], s->stream, f);
         if (st != GS_OK) return st;
     }
     hipError_t e = hipStreamSynchronize(s->stream);
@@ -506,7 +521,7 @@ gs_status gs_write(gs_sim *s, const double *u_host, const double *v_host)
     if (e != hipSuccess) return hip_fail(e, "gs_write sync");
     for (int f = 0; f < 2; ++f) {
         if (!srcs[f]) continue;
-        st = write_field(s->buf[s->parity][f], s->p.storage, s->n, srcs[f], s->stream);
+        st = write_field(s->buf[s->parity][f], s->p.storage, s->n, srcs[f], s->stream, f);
         if (st != GS_OK) return st;
     }
     return GS_OK;

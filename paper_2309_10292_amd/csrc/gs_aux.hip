@@ -23,8 +23,8 @@ __global__ __launch_bounds__(256) void init_cube_kernel(S *__restrict__ u, S *__
         typedef typename Traits<S>::C C;
         const C a = in ? (C)cu : (C)1;
         const C b = in ? (C)cv : (C)0;
-        u[i] = Traits<S>::store(a);
-        v[i] = Traits<S>::store(b);
+        u[i] = fstore<S>(0, a);
+        v[i] = fstore<S>(1, b);
     }
 }
 
@@ -45,6 +45,7 @@ hipError_t launch_init_cube(int storage, void *u, void *v, int nx, int ny, int n
     case 0: hipLaunchKernelGGL(init_cube_kernel<double>, dim3(g), dim3(256), 0, st, (double *)u, (double *)v, nx, ny, nz, side, cu, cv); break;
     case 1: hipLaunchKernelGGL(init_cube_kernel<float>, dim3(g), dim3(256), 0, st, (float *)u, (float *)v, nx, ny, nz, side, cu, cv); break;
     case 2: hipLaunchKernelGGL(init_cube_kernel<bf16>, dim3(g), dim3(256), 0, st, (bf16 *)u, (bf16 *)v, nx, ny, nz, side, cu, cv); break;
+    case 4: hipLaunchKernelGGL(init_cube_kernel<bf16c>, dim3(g), dim3(256), 0, st, (bf16c *)u, (bf16c *)v, nx, ny, nz, side, cu, cv); break;
     case 3: hipLaunchKernelGGL(init_cube_kernel<f16>, dim3(g), dim3(256), 0, st, (f16 *)u, (f16 *)v, nx, ny, nz, side, cu, cv); break;
     default: return hipErrorInvalidValue;
     }
@@ -66,8 +67,8 @@ __global__ __launch_bounds__(256) void init_box_kernel(S *__restrict__ u, S *__r
         const int dx = (x - x0 + nx) % nx, dy = (y - y0 + ny) % ny, dz = (z - z0 + nz) % nz;
         const bool in = dx < side && dy < side && dz < side;
         typedef typename Traits<S>::C C;
-        u[i] = Traits<S>::store(in ? (C)cu : (C)1);
-        v[i] = Traits<S>::store(in ? (C)cv : (C)0);
+        u[i] = fstore<S>(0, in ? (C)cu : (C)1);
+        v[i] = fstore<S>(1, in ? (C)cv : (C)0);
     }
 }
 
@@ -80,6 +81,7 @@ hipError_t launch_init_box(int storage, void *u, void *v, int nx, int ny, int nz
     case 0: hipLaunchKernelGGL(init_box_kernel<double>, dim3(g), dim3(256), 0, st, (double *)u, (double *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
     case 1: hipLaunchKernelGGL(init_box_kernel<float>, dim3(g), dim3(256), 0, st, (float *)u, (float *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
     case 2: hipLaunchKernelGGL(init_box_kernel<bf16>, dim3(g), dim3(256), 0, st, (bf16 *)u, (bf16 *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
+    case 4: hipLaunchKernelGGL(init_box_kernel<bf16c>, dim3(g), dim3(256), 0, st, (bf16c *)u, (bf16c *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
     case 3: hipLaunchKernelGGL(init_box_kernel<f16>, dim3(g), dim3(256), 0, st, (f16 *)u, (f16 *)v, nx, ny, nz, x0, y0, z0, side, cu, cv); break;
     default: return hipErrorInvalidValue;
     }
@@ -114,7 +116,9 @@ hipError_t launch_sqdiff(int storage, const void *a, const void *b, size_t n, do
     switch (storage) {
     case 0: hipLaunchKernelGGL(sqdiff_partial<double>, dim3(g), dim3(256), 0, st, (const double *)a, (const double *)b, n, part); break;
     case 1: hipLaunchKernelGGL(sqdiff_partial<float>, dim3(g), dim3(256), 0, st, (const float *)a, (const float *)b, n, part); break;
-    case 2: hipLaunchKernelGGL(sqdiff_partial<bf16>, dim3(g), dim3(256), 0, st, (const bf16 *)a, (const bf16 *)b, n, part); break;
+    case 2:
+    case 4: // (1 - a) - (1 - b) = b - a exactly: the complemented u needs no conversion here
+        hipLaunchKernelGGL(sqdiff_partial<bf16>, dim3(g), dim3(256), 0, st, (const bf16 *)a, (const bf16 *)b, n, part); break;
     case 3: hipLaunchKernelGGL(sqdiff_partial<f16>, dim3(g), dim3(256), 0, st, (const f16 *)a, (const f16 *)b, n, part); break;
     default: return hipErrorInvalidValue;
     }
@@ -200,10 +204,14 @@ __device__ Acc block_reduce(Acc a)
     return r;
 }
 
+// Stored value of field f (0 = u, 1 = v) as FP64 (for the complemented storage
+// 1 - stored u, exact in FP64).
 template <typename S>
-__device__ __forceinline__ double as_f64(S x)
+__device__ __forceinline__ double as_f64(int f, S x)
 {
-    return (double)Traits<S>::load(x);
+    const double d = (double)Traits<S>::load(x);
+    if constexpr (Complemented<S>::value) return f == 0 ? 1.0 - d : d;
+    else return d;
 }
 
 static constexpr int k_diag_blocks = 1024;
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(256) void diag_partial(const S *__restrict__ u, con
 {
     Acc a = acc_empty();
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const double x = as_f64(u[i]), y = as_f64(v[i]);
+        const double x = as_f64(0, u[i]), y = as_f64(1, v[i]);
         if (isfinite(x)) {
             neumaier_add(a.su, a.cu, x);
             a.mnu = fmin(a.mnu, x);
@@ -268,6 +276,7 @@ hipError_t launch_diagnostics(int storage, const void *u, const void *v, size_t 
     case 0: hipLaunchKernelGGL(diag_partial<double>, dim3(g), dim3(256), 0, st, (const double *)u, (const double *)v, n, part); break;
     case 1: hipLaunchKernelGGL(diag_partial<float>, dim3(g), dim3(256), 0, st, (const float *)u, (const float *)v, n, part); break;
     case 2: hipLaunchKernelGGL(diag_partial<bf16>, dim3(g), dim3(256), 0, st, (const bf16 *)u, (const bf16 *)v, n, part); break;
+    case 4: hipLaunchKernelGGL(diag_partial<bf16c>, dim3(g), dim3(256), 0, st, (const bf16c *)u, (const bf16c *)v, n, part); break;
     case 3: hipLaunchKernelGGL(diag_partial<f16>, dim3(g), dim3(256), 0, st, (const f16 *)u, (const f16 *)v, n, part); break;
     default: return hipErrorInvalidValue;
     }

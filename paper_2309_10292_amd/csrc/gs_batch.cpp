@@ -310,6 +310,8 @@ gs_status gs_batch_init(const gs_params *base, int32_t n_sims, const int32_t *nx
     if (base->tile > gs::num_tiles() + gs::num_tb_shapes() || base->tile < 0)
         return fail(GS_ERR_INVALID_ARG, "tile %d out of range", base->tile);
     if (base->tblock < 0 || base->tblock > GS_MAX_TBLOCK) return fail(GS_ERR_INVALID_ARG, "tblock out of range");
+    if (base->storage == GS_BF16C)
+        return fail(GS_ERR_UNSUPPORTED, "batched sweeps do not take the complemented BF16 storage");
     if (gs::tb_batch_max_T(base->tile ? base->tile - gs::num_tiles() : 2, base->storage) < 1)
         return fail(GS_ERR_UNSUPPORTED, "tile %d is not available to batched sweeps of this storage type", base->tile);
     if (base->tblock > gs::tb_batch_max_T(base->tile ? base->tile - gs::num_tiles() : 2, base->storage))
@@ -668,7 +670,7 @@ gs_status gs_batch_read(gs_batch *b, int32_t sim, double *u_host, double *v_host
     double *dst[2] = {u_host, v_host};
     for (int f = 0; f < 2; ++f) {
         if (!dst[f]) continue;
-        if ((st = read_field(s.buf[s.parity][f], b->base.storage, s.n, dst[f], b->stream)) != GS_OK) return st;
+        if ((st = read_field(s.buf[s.parity][f], b->base.storage, s.n, dst[f], b->stream, f)) != GS_OK) return st;
     }
     hipError_t e = hipStreamSynchronize(b->stream);
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_batch_read sync");
@@ -685,7 +687,7 @@ gs_status gs_batch_write(gs_batch *b, int32_t sim, const double *u_host, const d
     const double *srcs[2] = {u_host, v_host};
     for (int f = 0; f < 2; ++f) {
         if (!srcs[f]) continue;
-        if ((st = write_field(s.buf[s.parity][f], b->base.storage, s.n, srcs[f], b->stream)) != GS_OK) return st;
+        if ((st = write_field(s.buf[s.parity][f], b->base.storage, s.n, srcs[f], b->stream, f)) != GS_OK) return st;
     }
     return GS_OK;
 }

@@ -45,6 +45,30 @@ template <> struct Traits<bf16> {
     static __device__ __forceinline__ float load(bf16 s) { return to_f32(s); }
     static __device__ __forceinline__ bf16 store(float c) { return bf16_rne(c); }
 };
+// BF16 storage with u kept as its complement 1 - u (v as it is). Most of a
+// Gray-Scott state sits near u = 1, where BF16 steps are 2^-8 and the small
+// updates of a step are rounded away; 1 - u is near 0 there and BF16 keeps
+// eight significant bits of it. The same 2 bytes per value.
+struct bf16c {
+    uint16_t bits;
+};
+template <> struct Traits<bf16c> {
+    typedef float C;
+    static __device__ __forceinline__ float load(bf16c s) { return __uint_as_float((uint32_t)s.bits << 16); }
+    static __device__ __forceinline__ bf16c store(float c)
+    {
+        bf16c r;
+        r.bits = __builtin_bit_cast(uint16_t, (__bf16)c);
+        return r;
+    }
+};
+template <typename S> struct Complemented {
+    static constexpr bool value = false;
+};
+template <> struct Complemented<bf16c> {
+    static constexpr bool value = true;
+};
+
 template <> struct Traits<f16> {
     typedef float C;
     static __device__ __forceinline__ float load(f16 s) { return (float)s; }
@@ -175,6 +199,22 @@ __host__ __device__ __forceinline__ double div6(double x)
     const double f = __builtin_fma(r, h, q0);
     const double t = __builtin_fma(r, hu, q0);
     return __builtin_fma(f - t, -0.5, f);
+}
+
+// Field-aware conversions between storage and compute values (field 0 is u,
+// field 1 is v): the complemented storage type stores 1 - u. In FP32 1 - u is
+// exact for u in [1/2, 2], and the stored complement of a u below 1/2 (at
+// least 1/2) is rounded far more finely than by the storage.
+template <typename S> __device__ __forceinline__ typename Traits<S>::C fload(int f, S s)
+{
+    const typename Traits<S>::C c = Traits<S>::load(s);
+    if constexpr (Complemented<S>::value) return f == 0 ? 1.0f - c : c;
+    else return c;
+}
+template <typename S> __device__ __forceinline__ S fstore(int f, typename Traits<S>::C c)
+{
+    if constexpr (Complemented<S>::value) return Traits<S>::store(f == 0 ? 1.0f - c : c);
+    else return Traits<S>::store(c);
 }
 
 // Laplacian in FP32 from the differences d_i = n_i - c (exact when a

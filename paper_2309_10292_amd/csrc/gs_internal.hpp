@@ -16,8 +16,8 @@ bool aligned(const void *p, size_t a);
 // Validates a problem statement (grid, coefficients, init, tiling fields).
 gs_status validate(const gs_params *p);
 // Synchronising copies between a device field of `storage` type and host FP64.
-gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, hipStream_t st);
-gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, hipStream_t st);
+gs_status read_field(const void *dev, int32_t storage, size_t n, double *host, hipStream_t st, int field);
+gs_status write_field(void *dev, int32_t storage, size_t n, const double *host, hipStream_t st, int field);
 // Synchronising diagnostics of a (u, v) pair using the workspace's partials.
 gs_status diagnostics(int32_t storage, const void *u, const void *v, size_t n, void *ws, hipStream_t st,
                       gs_diag *out);

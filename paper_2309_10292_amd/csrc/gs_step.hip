@@ -98,25 +98,26 @@ __device__ __forceinline__ void load_ring(const S *__restrict__ f, size_t plane_
         out.e[0] = f[plane_off + m.halo_off];
 }
 
+// f: field index (0 = u, 1 = v), for the storage types that keep u complemented.
 template <typename S, int V, typename C>
-__device__ __forceinline__ void stage(C *__restrict__ L, const LaneMap &m, const C (&own)[V],
+__device__ __forceinline__ void stage(int f, C *__restrict__ L, const LaneMap &m, const C (&own)[V],
                                       const Vec<S, V> &ring)
 {
 #pragma unroll
     for (int i = 0; i < V; ++i) L[m.lds_own + i] = own[i];
     if (m.hkind == 1) {
 #pragma unroll
-        for (int i = 0; i < V; ++i) L[m.lds_halo + i] = Traits<S>::load(ring.e[i]);
+        for (int i = 0; i < V; ++i) L[m.lds_halo + i] = fload<S>(f, ring.e[i]);
     } else if (m.hkind == 2) {
-        L[m.lds_halo] = Traits<S>::load(ring.e[0]);
+        L[m.lds_halo] = fload<S>(f, ring.e[0]);
     }
 }
 
 template <typename S, int V, typename C>
-__device__ __forceinline__ void widen(const Vec<S, V> &a, C (&out)[V])
+__device__ __forceinline__ void widen(int f, const Vec<S, V> &a, C (&out)[V])
 {
 #pragma unroll
-    for (int i = 0; i < V; ++i) out[i] = Traits<S>::load(a.e[i]);
+    for (int i = 0; i < V; ++i) out[i] = fload<S>(f, a.e[i]);
 }
 
 // NF = 2: the Gray-Scott step on (u, v). NF = 1 with LAPLACE: out = lap(f)
@@ -146,12 +147,12 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        widen<S, V>(load_vec<S, V>(src[f], (size_t)wrap(z0 - 1, nz) * plane + m.own_off), zm[f]);
-        widen<S, V>(load_vec<S, V>(src[f], (size_t)z0 * plane + m.own_off), zc[f]);
-        widen<S, V>(load_vec<S, V>(src[f], (size_t)wrap(z0 + 1, nz) * plane + m.own_off), zp[f]);
+        widen<S, V>(f, load_vec<S, V>(src[f], (size_t)wrap(z0 - 1, nz) * plane + m.own_off), zm[f]);
+        widen<S, V>(f, load_vec<S, V>(src[f], (size_t)z0 * plane + m.own_off), zc[f]);
+        widen<S, V>(f, load_vec<S, V>(src[f], (size_t)wrap(z0 + 1, nz) * plane + m.own_off), zp[f]);
         Vec<S, V> r0;
         load_ring<S, V>(src[f], (size_t)z0 * plane, m, r0);
-        stage<S, V, C>(lds[0][f], m, zc[f], r0);
+        stage<S, V, C>(f, lds[0][f], m, zc[f], r0);
         if (z0 + 1 < ze) load_ring<S, V>(src[f], (size_t)wrap(z0 + 1, nz) * plane, m, ring[f]);
     }
     __syncthreads();
@@ -223,8 +224,8 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
                     // the FP32 sequence shared with the blocked kernels; r is n r
                     float uo, vo;
                     euler_f32<NOISE>(a.Du_f, a.Dv_f, a.F_f, a.FK_f, a.dt_f, uc, vc, lu, lv, r[i], uo, vo);
-                    ou.e[i] = Traits<S>::store(uo);
-                    ov.e[i] = Traits<S>::store(vo);
+                    ou.e[i] = fstore<S>(0, uo);
+                    ov.e[i] = fstore<S>(1, vo);
                 } else {
                     const C Du = Coef<C>::Du(a), Dv = Coef<C>::Dv(a), F = Coef<C>::F(a);
                     const C FK = Coef<C>::FK(a), dt = Coef<C>::dt(a);
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
         // Stage plane z+1 for the next iteration, then rotate the z window.
         if (z + 1 < ze) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) stage<S, V, C>(lds[buf ^ 1][f], m, zp[f], ring[f]);
+            for (int f = 0; f < NF; ++f) stage<S, V, C>(f, lds[buf ^ 1][f], m, zp[f], ring[f]);
         }
         __syncthreads();
 #pragma unroll
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
                 zm[f][i] = zc[f][i];
                 zc[f][i] = zp[f][i];
             }
-            widen<S, V>(pre[f], zp[f]);
+            widen<S, V>(f, pre[f], zp[f]);
             ring[f] = ring_next[f];
         }
         buf ^= 1;
@@ -295,7 +296,7 @@ int num_tiles() { return 4; }
 TileShape tile_shape(int tile, int storage)
 {
     if (tile < 1 || tile > 4) return TileShape{0, 0};
-    return (storage == 2 || storage == 3) ? k_tiles_w8[tile - 1] : k_tiles_w4[tile - 1];
+    return (storage == 2 || storage == 3 || storage == 4) ? k_tiles_w8[tile - 1] : k_tiles_w4[tile - 1];
 }
 
 template <typename S>
@@ -363,6 +364,7 @@ int step_occupancy(int storage, int tile, bool noise)
     case 1: return occ_w4<float>(tile, noise);
     case 2: return occ_w8<bf16>(tile, noise);
     case 3: return occ_w8<f16>(tile, noise);
+    case 4: return occ_w8<bf16c>(tile, noise);
     }
     return 0;
 }
@@ -375,6 +377,7 @@ hipError_t launch_step(int storage, int tile, const void *u, const void *v, void
     case 1: return dispatch_w4<float>(tile, u, v, un, vn, a, st);
     case 2: return dispatch_w8<bf16>(tile, u, v, un, vn, a, st);
     case 3: return dispatch_w8<f16>(tile, u, v, un, vn, a, st);
+    case 4: return dispatch_w8<bf16c>(tile, u, v, un, vn, a, st);
     }
     return hipErrorInvalidValue;
 }

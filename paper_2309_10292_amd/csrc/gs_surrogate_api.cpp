@@ -140,13 +140,16 @@ gs_status upload_fk(gs_surrogate *s, int32_t nsamp, const double *F, const doubl
     return e == hipSuccess ? GS_OK : hip_fail(e, "F/k upload");
 }
 
-// Planes per workgroup chunk of the convolutions: long chunks amortise the
-// two extra ring planes; shorter ones keep enough workgroups on small grids.
-int conv_zc(const gs_surrogate *s)
+// Planes per workgroup chunk of the convolutions for a batch of nsamp
+// samples: long chunks amortise the two extra ring planes (at 4 x 128^3 the
+// 32 -> 32 forward takes 0.757, 0.721 and 0.699 ms with 16, 32 and 64
+// planes), shorter ones keep at least 2048 workgroups (eight per CU) in flight
+// on small grids and batches.
+int conv_zc(const gs_surrogate *s, int nsamp)
 {
-    const int patches = (s->geo.nx / 16) * ((s->geo.ny + 3) / 4);
-    int zc = 32;
-    while (zc > 4 && (size_t)patches * ((s->geo.nz + zc - 1) / zc) < 2048) zc /= 2;
+    const size_t patches = (size_t)(s->geo.nx / 16) * ((s->geo.ny + 3) / 4) * (size_t)nsamp;
+    int zc = 64;
+    while (zc > 4 && patches * ((s->geo.nz + zc - 1) / zc) < 2048) zc /= 2;
     return zc < s->geo.nz ? zc : s->geo.nz;
 }
 
@@ -162,7 +165,7 @@ hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, co
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
-        a.zc = conv_zc(s);
+        a.zc = conv_zc(s, nsamp);
         a.in = in;
         a.wpack = at<uint16_t>(s, s->L.wf[l]);
         a.bias = P + b_off(l);
@@ -175,7 +178,7 @@ hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, co
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
-        a.zc = conv_zc(s);
+        a.zc = conv_zc(s, nsamp);
         a.in = in;
         a.wpack = at<uint16_t>(s, s->L.wf[3]);
         a.bias = P + b_off(3);
@@ -319,7 +322,7 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
         ConvArgs a = {};
         a.geo = s->geo;
         a.nsamp = nsamp;
-        a.zc = conv_zc(s);
+        a.zc = conv_zc(s, nsamp);
         a.in = dz;
         a.wpack = at<uint16_t>(s, s->L.wd[l]);
         a.zprev = at<uint16_t>(s, s->L.z[l - 1]);

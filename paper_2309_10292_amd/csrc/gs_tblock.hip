@@ -156,8 +156,8 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
         for (int f = 0; f < 2; ++f)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                win[0][2][f][e] = Traits<S>::load(q0[f].e[e]);
-                win[0][0][f][e] = Traits<S>::load(q1[f].e[e]);
+                win[0][2][f][e] = fload<S>(f, q0[f].e[e]);
+                win[0][0][f][e] = fload<S>(f, q1[f].e[e]);
             }
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -180,7 +180,7 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) win[0][slot3(P + 1)][f][e] = Traits<S>::load(pre[f].e[e]);
+            for (int e = 0; e < 4; ++e) win[0][slot3(P + 1)][f][e] = fload<S>(f, pre[f].e[e]);
         if (has && i + 2 <= ze + T - 1) load_plane(i + 2, pre);
 
         // Levels 1..T, in order; level k computes plane i-k+1.
@@ -237,8 +237,8 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                 C uo, vo;
                 cell_update<C, UNIT_DT, NOISE>(a, uc, vc, lu, lv, r[e], uo, vo);
                 // Intermediate levels carry the stored precision of the state.
-                res[0][e] = Traits<S>::load(Traits<S>::store(uo));
-                res[1][e] = Traits<S>::load(Traits<S>::store(vo));
+                res[0][e] = fload<S>(0, fstore<S>(0, uo));
+                res[1][e] = fload<S>(1, fstore<S>(1, vo));
             }
             if (k < T) {
 #pragma unroll
@@ -249,8 +249,8 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                 Vec<S, 4> ou, ov;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    ou.e[e] = Traits<S>::store(res[0][e]);
-                    ov.e[e] = Traits<S>::store(res[1][e]);
+                    ou.e[e] = fstore<S>(0, res[0][e]);
+                    ov.e[e] = fstore<S>(1, res[1][e]);
                 }
                 const size_t off = (size_t)zk * plane + xy;
                 NtStore<S>::put(un + off, ou);
@@ -472,6 +472,7 @@ template <bool BATCH> static int max_T_for(int shape, int storage)
     case 1: return tb_max_T_shape<float, BATCH>(shape);
     case 2: return tb_max_T_shape<bf16, BATCH>(shape);
     case 3: return tb_max_T_shape<f16, BATCH>(shape);
+    case 4: return BATCH ? 0 : tb_max_T_shape<bf16c, false>(shape);
     }
     return 0;
 }
@@ -617,6 +618,7 @@ int tb_occupancy(int storage, int T, int shape, bool noise)
     case 1: return occ_single_T<float>(T, shape, noise);
     case 2: return occ_single_T<bf16>(T, shape, noise);
     case 3: return occ_single_T<f16>(T, shape, noise);
+    case 4: return occ_single_T<bf16c>(T, shape, noise);
     }
     return 0;
 }
@@ -640,6 +642,7 @@ hipError_t launch_tblock(int storage, int T, int shape, const void *u, const voi
     case 1: return dispatch_tb_T<float>(T, shape, u, v, un, vn, a, st);
     case 2: return dispatch_tb_T<bf16>(T, shape, u, v, un, vn, a, st);
     case 3: return dispatch_tb_T<f16>(T, shape, u, v, un, vn, a, st);
+    case 4: return dispatch_tb_T<bf16c>(T, shape, u, v, un, vn, a, st);
     }
     return hipErrorInvalidValue;
 }

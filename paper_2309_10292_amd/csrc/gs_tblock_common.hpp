@@ -34,6 +34,14 @@ template <> struct NtStore<bf16> {
         __builtin_nontemporal_store(a, reinterpret_cast<u2 *>(p));
     }
 };
+template <> struct NtStore<bf16c> {
+    static __device__ __forceinline__ void put(bf16c *p, const Vec<bf16c, 4> &v)
+    {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        u2 a = {(unsigned)v.e[0].bits | ((unsigned)v.e[1].bits << 16), (unsigned)v.e[2].bits | ((unsigned)v.e[3].bits << 16)};
+        __builtin_nontemporal_store(a, reinterpret_cast<u2 *>(p));
+    }
+};
 template <> struct NtStore<f16> {
     static __device__ __forceinline__ void put(f16 *p, const Vec<f16, 4> &v)
     {

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "lib", "libgs.so")
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_UNSUPPORTED, GS_ERR_HIP, GS_ERR_NONFINITE, GS_ERR_STATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "GS_OK", -1: "GS_ERR_INVALID_ARG", -2: "GS_ERR_UNSUPPORTED", -3: "GS_ERR_HIP",
                 -4: "GS_ERR_NONFINITE", -5: "GS_ERR_STATE"}
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+# "bf16c": BF16 storage whose u buffers hold 1 - u (GS_BF16C)
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "bf16c": 4}
 INIT_NONE, INIT_CUBE = 0, 1
 MAX_TBLOCK = 4
 
@@ -164,7 +165,7 @@ def workspace_bytes(p: gs_params) -> int:
 
 def _torch_dtype(storage):
     import torch
-    return {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16}[storage]
+    return {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float16, 4: torch.bfloat16}[storage]
 
 
 def _stream_handle(stream=None):

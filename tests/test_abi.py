@@ -132,7 +132,7 @@ def test_workspace_and_tiles():
     n = L.gs_num_tiles()
     assert n >= 1
     for t in range(1, n + 1):
-        for s in range(4):
+        for s in range(5):
             tx, ty, mt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
             assert L.gs_tile_info(t, s, 1, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(mt)) == gs.GS_OK
             assert tx.value > 0 and ty.value > 0 and mt.value >= 1
@@ -154,6 +154,10 @@ def test_batch_max_tblock():
             mb = L.gs_batch_max_tblock(t, s)
             assert 0 <= mb <= gs.max_tblock(t, s) <= 4
     assert gs.max_tblock(6, "f64") == 4 and gs.max_tblock(6, "f64", batch=True) == 4
+    # the complemented BF16 storage is for single grids only
+    for t in range(5, n + 1):
+        assert L.gs_batch_max_tblock(t, 4) == 0
+        assert gs.max_tblock(t, "bf16c") == gs.max_tblock(t, "bf16")
 
 
 def test_noise_below_bound_rejected():

@@ -156,7 +156,7 @@ def test_deterministic_repeat(torch):
 
 
 def test_fixed_point_all_storage_types(torch):
-    for storage in ("f64", "f32", "bf16", "f16"):
+    for storage in ("f64", "f32", "bf16", "f16", "bf16c"):
         with _sim((16, 16, 16), storage=storage, cube_side=1, cube_u=1.0, cube_v=0.0, **P0) as s:
             s.step(10)
             u, v = s.read()
@@ -189,6 +189,32 @@ def test_16bit_rounding_ties_to_even(torch, storage):
         assert np.all(u[:6] == 1.0) and np.all(v[:6] == 0.0)
 
 
+def test_bf16c_stores_the_complement_of_u(torch):
+    """The complemented BF16 storage keeps 1 - u: u = 1 - 3 2^-12 (1 - u has
+    two significant bits) survives the cube initialisation, a host write and
+    read, and the diagnostics exactly, where plain BF16 (steps of 2^-9 below
+    1) rounds it to 1; v is plain BF16."""
+    cu, cv = 1.0 - 3 * 2.0 ** -12, 0.25
+    with _sim((16, 16, 16), storage="bf16", cube_side=4, cube_u=cu, cube_v=cv) as s:
+        u, _ = s.read()
+    assert u[8, 8, 8] == 1.0
+    with _sim((16, 16, 16), storage="bf16c", cube_side=4, cube_u=cu, cube_v=cv) as s:
+        u, v = s.read()
+        c = slice(6, 10)
+        assert np.all(u[c, c, c] == cu) and np.all(v[c, c, c] == cv)
+        assert np.all(u[:6] == 1.0) and np.all(v[:6] == 0.0)
+        ut, vt, _ = s.current()  # the raw u buffer holds 1 - u
+        raw = ut.float().cpu().numpy()
+        assert np.all(raw[c, c, c] == 3 * 2.0 ** -12) and np.all(raw[:6] == 0.0)
+        d = s.diagnostics()
+        assert d["min_u"] == cu and d["max_u"] == 1.0 and d["max_v"] == cv
+        assert d["sum_u"] == 16 ** 3 - 64 * 3 * 2.0 ** -12
+        w = np.full((16, 16, 16), 1.0 - 5 * 2.0 ** -14)
+        s.write(w, v)
+        u2, v2 = s.read()
+        assert np.array_equal(u2, w) and np.array_equal(v2, v)
+
+
 def test_diagnostics_vs_oracle(torch, small_ref):
     p = workload("small_l64")
     with _sim((64, 64, 64), **P0) as s:
@@ -216,7 +242,7 @@ def test_diagnostics_vs_oracle(torch, small_ref):
 def test_reduced_precision_within_bars(torch, small_ref):
     """FP32 / FP16 / BF16 storage (FP32 arithmetic, compensated Laplacian) on
     the L=64 workload, 100 steps, against the FP64 oracle."""
-    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}
+    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2, "bf16c": 5e-2}
     p = workload("small_l64")
     for storage, bar in bars.items():
         with _sim((64, 64, 64), storage=storage, **P0) as s:
@@ -233,7 +259,7 @@ def test_reduced_precision_with_noise_l64(torch):
     The storage types round the noise like every other update: FP32 keeps it
     to about 1e-7 of u near 1, FP16 to half of 2^-10 and BF16 to half of 2^-7,
     so the bars are those of the noise-free L=64 run."""
-    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}
+    bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2, "bf16c": 5e-2}
     p = dict(workload("small_l64"), noise=1e-3, seed=77)
     u0, v0 = O.init_cube(L=64)
     ue, ve = O.run(u0, v0, p["steps"], **p)
@@ -372,7 +398,7 @@ def test_tblock_small_l64_fp64_bitwise(torch, small_ref):
             assert np.array_equal(u, small_ref[0]) and np.array_equal(v, small_ref[1]), (T, tile)
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "bf16c"])
 def test_tblock_reduced_precision_equals_single_step(torch, storage):
     """Reduced-precision storage: T fused steps round every intermediate level
     to the storage type, so they equal T single-step sweeps bit for bit."""
