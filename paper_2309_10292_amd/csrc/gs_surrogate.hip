@@ -246,6 +246,255 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
     }
 }
 
+// 32 -> 32 convolutions of the forward hidden layer and the data gradient,
+// with every weight fragment in registers. A wavefront owns RW rows of 16
+// cells and both 16-channel N tiles (four accumulator chains) of one sample
+// and marches through a chunk of z planes with a private LDS ring of four
+// input planes (rows y-1 .. y+RW, cells x-1 .. x+16, channel group major),
+// so the wavefronts of a workgroup never wait for each other. The K loop
+// reads only activation fragments from LDS, one per row and K chunk for two
+// MFMAs. Plane z's MFMAs and plane z-1's epilogue (bias, GELU or its
+// derivative, BF16 rounding) sit in one basic block, so the vector units
+// work while the matrix cores run. The MFMAs accumulate each output over the
+// 27 K chunks in the same order as conv_kernel, so the results are the same
+// bit for bit.
+constexpr int C32_RW = 2, C32_WAVES = 4;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4))); // a native vector (no struct copies)
+template <bool B> struct BoolC {
+    static constexpr bool value = B;
+};
+template <int MODE>
+__global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void conv32p_kernel(ConvArgs a)
+{
+    constexpr int NT = 2, NCH = 27, VPC = 4, RW = C32_RW, PYW = RW * C32_WAVES;
+    constexpr int RCELLS = RX * (RW + 2);              // ring cells per plane
+    constexpr int GC = (RCELLS + 15) / 16 * 16;        // cells per channel group, padded to 256 bytes
+    constexpr int SLOT_V = GC * VPC;                   // 16-byte vectors per plane slot
+    constexpr int LOAD_V = RCELLS * VPC;               // vectors loaded per plane
+    constexpr int LOADS = (LOAD_V + 63) / 64;
+    __shared__ u32x4 ring_all[C32_WAVES * 4 * SLOT_V];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u32x4 *ring = ring_all + wave * 4 * SLOT_V;
+    const int col = lane & 15, quad = lane >> 4;
+    const Geo g = a.geo;
+
+    bf16x8 wr[NCH][NT];
+    {
+        const uint4 *wg = reinterpret_cast<const uint4 *>(a.wpack);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) wr[c][t] = __builtin_bit_cast(bf16x8, wg[(c * NT + t) * 64 + lane]);
+    }
+    const int tx = g.nx / PX, ty = (g.ny + PYW - 1) / PYW, tzc = (g.nz + a.zc - 1) / a.zc;
+    int b = blockIdx.x;
+    const int bx = b % tx;
+    b /= tx;
+    const int by = b % ty;
+    b /= ty;
+    const int bz = b % tzc;
+    const int s = b / tzc;
+    const int x0 = bx * PX, yw = by * PYW + RW * wave, z0 = bz * a.zc;
+    const int ze = min(z0 + a.zc, g.nz);
+    if (yw >= g.ny) return; // a wavefront below the grid (no barriers in this kernel)
+    const size_t sbase = (size_t)s * g.ncell, plane = (size_t)g.nx * g.ny;
+
+    // This lane's ring vectors: offset within an input plane (in channels)
+    // and ring position; the lanes past the plane load a valid vector and
+    // store nothing.
+    size_t goff[LOADS];
+    int rpos[LOADS];
+#pragma unroll
+    for (int l = 0; l < LOADS; ++l) {
+        const int v = min(lane + 64 * l, LOAD_V - 1);
+        const int cell = v / VPC, cg = v % VPC;
+        const int rx = cell % RX, ry = cell / RX;
+        int gy = yw + ry - 1;
+        if (gy < 0) gy += g.ny;
+        while (gy >= g.ny) gy -= g.ny;
+        const int gx = wrapc(x0 + rx - 1, g.nx);
+        goff[l] = ((size_t)gx + (size_t)g.nx * gy) * 32 + cg * 8;
+        // lanes past the plane store into the padding cells of channel group 3
+        rpos[l] = lane + 64 * l < LOAD_V ? cg * GC + cell : 3 * GC + RCELLS + (lane & (GC - RCELLS - 1));
+    }
+    auto load_plane = [&](int z, u32x4 (&o)[LOADS]) __attribute__((always_inline)) {
+        const uint16_t *base = a.in + (sbase + (size_t)wrapc(z, g.nz) * plane) * 32;
+#pragma unroll
+        for (int l = 0; l < LOADS; ++l) o[l] = *reinterpret_cast<const u32x4 *>(base + goff[l]);
+    };
+    auto stage_plane = [&](int z, const u32x4 (&o)[LOADS]) __attribute__((always_inline)) {
+        u32x4 *dst = ring + (z & 3) * SLOT_V;
+#pragma unroll
+        for (int l = 0; l < LOADS; ++l) dst[rpos[l]] = o[l];
+    };
+    // Epilogue values: the lane's biases are read once (the compiler cannot
+    // move their loads past the output stores).
+    float bias_r[NT][4] = {};
+    if constexpr (MODE == MODE_HIDDEN) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bias_r[t][j] = a.bias[16 * t + 4 * quad + j];
+    }
+    auto cell_of = [&](int r, int z) __attribute__((always_inline)) {
+        const int yrow = min(yw + r, g.ny - 1);
+        return sbase + (size_t)(x0 + col) + (size_t)g.nx * ((size_t)yrow + (size_t)g.ny * wrapc(z, g.nz));
+    };
+    // One plane: start loading plane z+2, run the 27 K chunks of plane z,
+    // then stage plane z+2 into the ring; with PREV, the
+    // previous plane's 16 epilogue values (2 rows x 2 tiles x 4 channels) are
+    // computed one per chunk beside its MFMAs, and stored at the end.
+    auto plane_step = [&](auto prev, int z, f32x4 (&acc)[RW][NT], const f32x4 (&accp)[RW][NT], u32x4 (&pre)[LOADS]) __attribute__((always_inline)) {
+        constexpr bool PREV = decltype(prev)::value;
+        load_plane(z + 2, pre);
+        uint2 zq[RW][NT];
+        if constexpr (PREV && MODE == MODE_DGRAD) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    zq[r][t] = *reinterpret_cast<const uint2 *>(a.zprev + cell_of(r, z - 1) * 32 + 16 * t + 4 * quad);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        constexpr int KD = 3;
+        bf16x8 av[KD][RW];
+        auto frag = [&](int c, int sl) __attribute__((always_inline)) {
+            const int dz = c / 9, dy = (c / 3) % 3, dx = c % 3;
+            const u32x4 *rs = ring + ((z + dz - 1) & 3) * SLOT_V + quad * GC;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) av[sl][r] = __builtin_bit_cast(bf16x8, rs[(r + dy) * RX + col + dx]);
+        };
+#pragma unroll
+        for (int c = 0; c < KD; ++c) frag(c, c);
+        u16 e1[RW][NT][4], e2[RW][NT][4];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int sl = c % KD;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[c][t], av[sl][r], acc[r][t], 0, 0, 0);
+            if (c + KD < NCH) frag(c + KD, sl);
+            if constexpr (PREV) {
+                if (c < RW * NT * 4) {
+                    const int r = c / (NT * 4), t = (c / 4) % NT, j = c % 4;
+                    // the empty asm keeps each value's arithmetic at this chunk
+                    // (pure arithmetic would otherwise sink to the stores)
+                    if constexpr (MODE == MODE_HIDDEN) {
+                        float zz = accp[r][t][j] + bias_r[t][j];
+                        float gz = gelu(zz);
+                        asm volatile("" : "+v"(zz), "+v"(gz));
+                        e1[r][t][j] = f2bf(zz);
+                        e2[r][t][j] = f2bf(gz);
+                    } else {
+                        const uint32_t w = j < 2 ? zq[r][t].x : zq[r][t].y;
+                        const float zp = bf2f((u16)((j & 1) ? (w >> 16) : (w & 0xffffu)));
+                        float gd = accp[r][t][j] * gelu_grad(zp);
+                        asm volatile("" : "+v"(gd));
+                        e1[r][t][j] = f2bf(gd);
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // plane z+2 into its slot (last read as plane z-2), before the stores
+        // so that the wait for its loads does not also wait for them
+        stage_plane(z + 2, pre);
+        if constexpr (PREV) {
+            // rows last to first: a row past the grid (only when ny is odd) is
+            // clamped onto row 0's cell, whose own store then follows it
+#pragma unroll
+            for (int r = RW - 1; r >= 0; --r) {
+                const size_t cell = cell_of(r, z - 1);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int co0 = 16 * t + 4 * quad;
+                    const uint2 q1{(uint32_t)e1[r][t][0] | ((uint32_t)e1[r][t][1] << 16),
+                                   (uint32_t)e1[r][t][2] | ((uint32_t)e1[r][t][3] << 16)};
+                    if constexpr (MODE == MODE_HIDDEN) {
+                        const uint2 q2{(uint32_t)e2[r][t][0] | ((uint32_t)e2[r][t][1] << 16),
+                                       (uint32_t)e2[r][t][2] | ((uint32_t)e2[r][t][3] << 16)};
+                        *reinterpret_cast<uint2 *>(a.zout + cell * 32 + co0) = q1;
+                        *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) = q2;
+                    } else {
+                        *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) = q1;
+                    }
+                }
+            }
+        }
+    };
+    // The last plane's epilogue on its own.
+    auto last_epilogue = [&](int z, const f32x4 (&accp)[RW][NT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = RW - 1; r >= 0; --r) {
+            const size_t cell = cell_of(r, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int co0 = 16 * t + 4 * quad;
+                u16 e1[4], e2[4];
+                if constexpr (MODE == MODE_HIDDEN) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float zz = accp[r][t][j] + bias_r[t][j];
+                        e1[j] = f2bf(zz);
+                        e2[j] = f2bf(gelu(zz));
+                    }
+                    *reinterpret_cast<uint2 *>(a.zout + cell * 32 + co0) =
+                        uint2{(uint32_t)e1[0] | ((uint32_t)e1[1] << 16), (uint32_t)e1[2] | ((uint32_t)e1[3] << 16)};
+                    *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) =
+                        uint2{(uint32_t)e2[0] | ((uint32_t)e2[1] << 16), (uint32_t)e2[2] | ((uint32_t)e2[3] << 16)};
+                } else {
+                    const uint2 zq = *reinterpret_cast<const uint2 *>(a.zprev + cell * 32 + co0);
+                    const float zp[4] = {bf2f((u16)(zq.x & 0xffffu)), bf2f((u16)(zq.x >> 16)),
+                                         bf2f((u16)(zq.y & 0xffffu)), bf2f((u16)(zq.y >> 16))};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) e1[j] = f2bf(accp[r][t][j] * gelu_grad(zp[j]));
+                    *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) =
+                        uint2{(uint32_t)e1[0] | ((uint32_t)e1[1] << 16), (uint32_t)e1[2] | ((uint32_t)e1[3] << 16)};
+                }
+            }
+        }
+    };
+
+    u32x4 pre[LOADS];
+    {
+        u32x4 q[LOADS];
+        for (int p = -1; p <= 1; ++p) {
+            load_plane(z0 + p, q);
+            stage_plane(z0 + p, q);
+        }
+    }
+    f32x4 accA[RW][NT], accB[RW][NT];
+    plane_step(BoolC<false>{}, z0, accA, accB, pre);
+    int z = z0 + 1;
+    for (; z + 1 < ze; z += 2) {
+        plane_step(BoolC<true>{}, z, accB, accA, pre);
+        plane_step(BoolC<true>{}, z + 1, accA, accB, pre);
+    }
+    if (z < ze) {
+        plane_step(BoolC<true>{}, z, accB, accA, pre);
+        last_epilogue(z, accB);
+    } else {
+        last_epilogue(ze - 1, accA);
+    }
+}
+// Planes per workgroup of conv32p_kernel: one workgroup of four wavefronts
+// fills a CU (its registers), so the chunk is the longest that still gives at
+// least two workgroups per CU, which amortises the weights' load and the ring's
+// first planes.
+int conv32p_zc(const Geo &g, int nsamp)
+{
+    const size_t cols = (size_t)(g.nx / PX) * ((g.ny + C32_RW * C32_WAVES - 1) / (C32_RW * C32_WAVES)) * (size_t)nsamp;
+    int zc = 1;
+    while (zc < g.nz) zc *= 2;
+    while (zc > 4 && cols * ((g.nz + zc - 1) / zc) < 512) zc /= 2;
+    return zc;
+}
+
 // ------------------------------------------------------------------ weight gradient
 // dW[d][co][ci] = sum over cells of dz[cell][co] * act[neighbour(cell, d)][ci].
 // A = dz^T (rows co, K = cells), B = act (K = cells, columns ci): both MFMA
@@ -597,16 +846,26 @@ static int grid_cap(size_t work, int per_block, int cap)
 hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a, hipStream_t st)
 {
     if (a.zc < 1 || a.geo.nx % PX != 0) return hipErrorInvalidValue;
+    if (cin == 32 && nt == 2 && mode != MODE_OUT) {
+        ConvArgs b = a;
+        b.zc = conv32p_zc(a.geo, a.nsamp);
+        const int py = C32_RW * C32_WAVES;
+        const size_t nb = (size_t)(a.geo.nx / PX) * ((a.geo.ny + py - 1) / py) * ((a.geo.nz + b.zc - 1) / b.zc) * a.nsamp;
+        if (nb == 0 || nb > 0x7fffffffu) return hipErrorInvalidConfiguration;
+        if (mode == MODE_HIDDEN)
+            hipLaunchKernelGGL(conv32p_kernel<MODE_HIDDEN>, dim3((unsigned)nb), dim3(64 * C32_WAVES), 0, st, b);
+        else
+            hipLaunchKernelGGL(conv32p_kernel<MODE_DGRAD>, dim3((unsigned)nb), dim3(64 * C32_WAVES), 0, st, b);
+        return hipGetLastError();
+    }
     const size_t blocks = (size_t)(a.geo.nx / PX) * ((a.geo.ny + PY - 1) / PY) * ((a.geo.nz + a.zc - 1) / a.zc) * a.nsamp;
     if (blocks == 0 || blocks > 0x7fffffffu) return hipErrorInvalidConfiguration;
     const int grid = (int)blocks;
 #define GS_CONV(CI, N, M, IO) hipLaunchKernelGGL((conv_kernel<CI, N, M, IO>), dim3(grid), dim3(256), 0, st, a)
     if (cin == 8 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(8, 2, MODE_HIDDEN, float);
-    else if (cin == 32 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(32, 2, MODE_HIDDEN, float);
     else if (cin == 32 && nt == 1 && mode == MODE_OUT && io_f64) GS_CONV(32, 1, MODE_OUT, double);
     else if (cin == 32 && nt == 1 && mode == MODE_OUT) GS_CONV(32, 1, MODE_OUT, float);
     else if (cin == 8 && nt == 2 && mode == MODE_DGRAD) GS_CONV(8, 2, MODE_DGRAD, float);
-    else if (cin == 32 && nt == 2 && mode == MODE_DGRAD) GS_CONV(32, 2, MODE_DGRAD, float);
     else return hipErrorInvalidValue;
 #undef GS_CONV
     return hipGetLastError();

@@ -22,7 +22,7 @@ struct Geo {
 struct ConvArgs {
     Geo geo;
     int nsamp;
-    int zc;                 // planes per workgroup chunk
+    int zc;                 // planes per workgroup chunk (the 32 -> 32 hidden and data-gradient kernels pick their own)
     const uint16_t *in;     // channels-last BF16 input (CIN channels)
     const uint16_t *wpack;  // packed BF16 weights (B fragments)
     const float *bias;      // MODE_HIDDEN / MODE_OUT
