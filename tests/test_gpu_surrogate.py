@@ -60,14 +60,18 @@ def _fields(shape, n, seed):
     return u, v
 
 
-def test_forward_matches_oracle(torch):
+@pytest.mark.parametrize("shape", [(8, 12, 16), (6, 7, 32)])
+def test_forward_matches_oracle(torch, shape):
+    """The forward pass against the oracle; (6, 7, 32) has two x-patches and
+    an odd number of rows, so a wavefront of the two-row kernels holds a row
+    past the grid."""
     from paper_2309_10292_amd.surrogate import Surrogate
-    shape = (8, 12, 16)
     n = 2
     p32 = _params(3)
     u, v = _fields(shape, n, 4)
     F, k = np.array([0.02, 0.05]), np.array([0.048, 0.062])
-    with Surrogate(16, 12, 8, max_batch=n, params=p32) as m:
+    nz, ny, nx = shape
+    with Surrogate(nx, ny, nz, max_batch=n, params=p32) as m:
         ut = torch.from_numpy(u).cuda()
         vt = torch.from_numpy(v).cuda()
         pu, pv = m.predict(ut, vt, F, k)
