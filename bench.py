@@ -55,14 +55,15 @@ ERR_STEPS = 1000  # run length of the L=512 workload, at which the variants' err
 def alu_ops_per_cell_update(storage, noise):
     """Vector instructions the FP64 step needs per cell-update on this
     hardware: per field, the Laplacian is 5 adds, the product 6c, the
-    subtraction and the division by 6 (6 operations for the correctly rounded
-    quotient), 13 in all; the reaction, feed and kill terms and the Euler
-    update (dt = 1) take 13 more. With noise, one Philox4x32-10 block per 4
-    cells (10 rounds of two 32x32->64-bit products and two three-input XORs)
-    plus the word's conversion, the fused noise term and its addition: 13."""
+    subtraction and the division by 6 (4 operations for the correctly rounded
+    quotient: a product, two fmas and the shift-or that picks the multiplier),
+    11 in all; the reaction, feed and kill terms and the Euler update (dt = 1)
+    take 13 more. With noise, one Philox4x32-10 block per 4 cells (10 rounds
+    of two 32x32->64-bit products and two three-input XORs) plus the word's
+    conversion, the fused noise term and its addition: 13."""
     if storage != "f64":
         return None
-    return 2 * 13 + 13 + (13 if noise else 0)
+    return 2 * 11 + 13 + (13 if noise else 0)
 
 
 def kernel_name(cfg, storage, noise):

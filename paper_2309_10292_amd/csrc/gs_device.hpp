@@ -170,35 +170,37 @@ __device__ __forceinline__ Philox4 noise_block(uint64_t idx4, uint64_t t, uint64
 // quotient, bit for bit, for every finite x (a zero gives +0).
 //
 // With h = RN(1/6) and q0 = RN(x h), the residual r = x - 6 q0 is a small
-// multiple of ulp(q0) and so exact in one fma, and x / 6 = q0 + r / 6.
-// f = RN(q0 + r h) rounds that sum with r h in place of r / 6, off by
-// r (h - 1/6). Where the quotient is normal, x / 6 = m ulp(x) / 6 for an
-// integer m is never closer than ulp(x) / 48 to a rounding boundary (odd
-// multiples of ulp(x) / 16 or / 8, which would need m divisible by 3 and an
-// even multiplier at once), while r (h - 1/6) is below 2 ulp(x) 2^-56, so f
-// is the quotient. Where it is subnormal, its grid is the fixed step 2^-1074
-// and x / 6 can lie exactly half-way between two grid points (x an odd
-// multiple of 3 2^-1074); the small perturbation then decides the rounding
-// instead of the tie rule, and f lands on q0 whatever its parity. Such
-// arguments are common: a field decaying towards 0 has subnormal tails.
-//
-// The tie is resolved without a branch: t = RN(q0 + r h') with h' the
-// double just above 1/6 (h is just below) rounds the same as f except on an
-// exact tie, where f and t are the two grid points around x / 6. Then
-// RN(f + (t - f) / 2), formed as one fma of the exact difference f - t, is f
-// away from ties and the tie x / 6 itself rounded to even. The fma's
-// product is -0 when f == t, which keeps a -0 quotient of a tiny negative x.
+// multiple of ulp(q0) (|r| <= 3 ulp(q0) and a little) and so exact in one
+// fma, and x / 6 = q0 + r / 6. The quotient is RN(q0 + r c) for any c close
+// enough to 1/6, except on an exact tie:
+//  - Away from ties. x is an integer multiple of an ulp at least four times
+//    the quotient's (x / 6 < x / 4), and of 2^-1074 where the quotient is
+//    subnormal, so x / 6 sits at a multiple of 1/6 of the quotient's grid
+//    step from a grid point and at least 1/6 of a step from every rounding
+//    boundary. r (c - 1/6) moves it by at most 3 |c - 1/6| steps, far less
+//    for |c - 1/6| <= 2^-23.
+//  - Ties. Only a subnormal quotient can lie exactly half-way between two
+//    grid points (x an odd multiple of 3 2^-1074); q0 is one of the two and
+//    r = +-3 steps. RN(q0 + r c) is q0 for c below 1/6 and the other point
+//    for c above it, while the rule wants the even one.
+// So c is taken just below 1/6 when q0's last significand bit is 0 and just
+// above it when that bit is 1: its high word is 0x3FC55555 and its low word
+// the same constant with q0's last bit moved to bit 31 (0x3FC55555 or
+// 0xBFC55555, both within 2^-24 of 1/6), one shift-or. The same constant in
+// both words lets one register serve as the shift-or's operand and as the
+// multiplier's high half. A tiny negative x gives RN(-0 + r c) = -0, as the
+// division does.
 // A numerator of +-Inf (an infinite input, or a neighbour sum beyond the
 // largest double) gives NaN where the division gives +-Inf.
 __host__ __device__ __forceinline__ double div6(double x)
 {
-    const double h = 0x1.5555555555555p-3;  // RN(1/6), just below 1/6
-    const double hu = 0x1.5555555555556p-3; // the next double, just above 1/6
+    const double h = 0x1.5555555555555p-3; // RN(1/6), just below 1/6
     const double q0 = x * h;
     const double r = __builtin_fma(-q0, 6.0, x);
-    const double f = __builtin_fma(r, h, q0);
-    const double t = __builtin_fma(r, hu, q0);
-    return __builtin_fma(f - t, -0.5, f);
+    const uint32_t k = 0x3FC55555u;
+    const uint32_t lo = ((uint32_t)__builtin_bit_cast(uint64_t, q0) << 31) | k;
+    const double c = __builtin_bit_cast(double, ((uint64_t)k << 32) | lo);
+    return __builtin_fma(r, c, q0);
 }
 
 // Field-aware conversions between storage and compute values (field 0 is u,

@@ -12,7 +12,9 @@
 // are all shallower than level k skips level k as a whole.
 //
 // Per z iteration i (a wavefront in z):
-//   - level-0 plane i+1 enters (prefetched one iteration earlier);
+//   - level-0 plane i+1 enters (prefetched one iteration earlier, into
+//     registers or, in the FP64 kernel with noise at three fused steps,
+//     straight into a lane-private LDS area);
 //   - for k = 1..T, level k computes plane i-k+1 from level k-1's planes
 //     i-k, i-k+1, i-k+2: z neighbours from the lane's registers (three plane
 //     slots per level; plane z sits in slot (z - i0) mod 3, and the loop is
@@ -29,6 +31,27 @@
 #include "gs_tblock_common.hpp"
 
 namespace gs {
+
+// The FP64 kernel with noise at three fused steps and 512 lanes prefetches
+// level 0 through LDS (global_load_lds, 16 bytes per lane and load) instead
+// of registers, and makes the next iteration's Philox blocks between the two
+// barriers of an iteration, where the vector units otherwise wait for the
+// LDS stores: the registers this frees keep its straight-line levels free of
+// spills.
+template <typename S, int T, int NT, bool NOISE, bool BATCH> constexpr bool tb_dma()
+{
+    return sizeof(S) == 8 && NOISE && !BATCH && T == 3 && NT == 512;
+}
+// A workgroup barrier that waits for the LDS operations only: the LDS-DMA
+// prefetch stays in flight across it (each wave reads only the area its own
+// loads fill, after waiting for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 template <typename S, int TXG, int TY, int T, int NT> struct TbGeom {
     typedef typename Traits<S>::C C;
@@ -72,15 +95,19 @@ template <typename S, int TXG, int TY, int T, int NT> struct TbGeom {
 
 // One output tile [x0, x0 + 4 TXG) x [y0, y0 + TY) x [z0, ze) of a grid
 // (a.nx, a.ny, a.nz), T steps from (u, v) into (un, vn); t0 is the step index
-// of the first of the T steps. `lds` holds 2 * TbGeom::FIELD elements. Every
-// lane of the workgroup must call it (it contains barriers).
+// of the first of the T steps. `lds` holds 2 * TbGeom::FIELD elements and
+// `pre_lds` 4 * NT 16-byte slots where tb_dma() holds (else it is unused).
+// Every lane of the workgroup must call it (it contains barriers).
 template <typename S, int TXG, int TY, int T, int NT, bool NOISE, bool BATCH, bool UNIT_DT>
 __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__restrict__ v, S *__restrict__ un,
                                         S *__restrict__ vn, const StepArgs &a, int x0, int y0, int z0, int ze,
-                                        uint64_t t0, typename Traits<S>::C *__restrict__ lds)
+                                        uint64_t t0, typename Traits<S>::C *__restrict__ lds,
+                                        uint4 *__restrict__ pre_lds)
 {
     typedef TbGeom<S, TXG, TY, T, NT> G;
     typedef typename G::C C;
+    constexpr bool DMA = tb_dma<S, T, NT, NOISE, BATCH>();
+    static_assert(!DMA || 2 * G::FIELD * sizeof(C) + 4 * NT * 16 <= 160 * 1024, "staged planes and prefetch fit");
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t plane = (size_t)nx * (size_t)ny;
 
@@ -142,16 +169,55 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
     };
     auto in_level = [&](int k) { return dep >= k; };
 
+    // LDS-DMA prefetch (tb_dma): slot 2 f + hh of a lane holds cells
+    // 2 hh, 2 hh + 1 of field f; a wave's 64 lanes fill 64 consecutive slots.
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    auto dma_plane = [&](int z) {
+        const size_t off = (size_t)wrap(z, nz) * plane + xy;
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+                __builtin_amdgcn_global_load_lds((const void *)(src[f] + off + 2 * hh),
+                                                 (__attribute__((address_space(3))) void *)(pre_lds + (2 * f + hh) * NT +
+                                                                                            64 * wave),
+                                                 16, 0, 0);
+    };
+    auto read_pre = [&](C (&o)[2][4]) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const double2 q = *reinterpret_cast<const double2 *>(pre_lds + (2 * f + hh) * NT + threadIdx.x);
+                o[f][2 * hh] = q.x;
+                o[f][2 * hh + 1] = q.y;
+            }
+    };
+    // Philox blocks of the next iteration's levels (tb_dma), made ahead.
+    uint32_t wq[T][4];
+    auto make_noise = [&](const int i, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+#pragma unroll
+        for (int k = 1; k <= T; ++k) {
+            if (!FULL && !in_level(k)) continue;
+            const size_t idx = (size_t)wrap(i - k + 1, nz) * plane + xy;
+            const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) wq[k - 1][e] = w.w[e];
+        }
+    };
+
     // Prologue: level-0 slots hold planes i0-1 (slot 2) and i0 (slot 0); plane
     // i0+1 is in flight; LDS holds level-0 plane i0.
     const int i0 = z0 - T + 1;
     const int i_end = ze + T - 2; // inclusive
     Vec<S, 4> pre[2];
+    if constexpr (DMA) dma_plane(i0 + 1);
     if (has) {
         Vec<S, 4> q0[2], q1[2];
         load_plane(i0 - 1, q0);
         load_plane(i0, q1);
-        load_plane(i0 + 1, pre);
+        if constexpr (!DMA) load_plane(i0 + 1, pre);
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
@@ -164,7 +230,12 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
 #pragma unroll
             for (int e = 0; e < 4; ++e) lds_at(f, 0, rys, e) = win[0][0][f][e];
     }
-    __syncthreads();
+    if constexpr (DMA) {
+        make_noise(i0, Full<true>{});
+        lds_barrier();
+    } else {
+        __syncthreads();
+    }
 
     // One z iteration at phase P = (i - i0) mod 3. A wave whose first lane
     // (the deepest position of the wave) has depth T runs every level on all
@@ -177,11 +248,18 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
         constexpr int P = decltype(phase)::value;
         constexpr bool FULL = decltype(full)::value;
         // Level 0: plane i+1 enters its slot; prefetch plane i+2.
+        if constexpr (DMA) {
+            __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0): this wave's prefetch has landed
+            read_pre(win[0][slot3(P + 1)]);
+            __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0): read before it is overwritten
+            if (i + 2 <= ze + T - 1) dma_plane(i + 2);
+        } else {
 #pragma unroll
-        for (int f = 0; f < 2; ++f)
+            for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) win[0][slot3(P + 1)][f][e] = fload<S>(f, pre[f].e[e]);
-        if (has && i + 2 <= ze + T - 1) load_plane(i + 2, pre);
+                for (int e = 0; e < 4; ++e) win[0][slot3(P + 1)][f][e] = fload<S>(f, pre[f].e[e]);
+            if (has && i + 2 <= ze + T - 1) load_plane(i + 2, pre);
+        }
 
         // Levels 1..T, in order; level k computes plane i-k+1.
 #pragma unroll
@@ -207,8 +285,13 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
             }
             C r[4] = {(C)0, (C)0, (C)0, (C)0}; // the noise term n r
             if constexpr (NOISE) {
-                const size_t idx = (size_t)wrap(zk, nz) * plane + xy;
-                const Philox4 w = noise_block(idx, t0 + (uint64_t)(k - 1), a.seed);
+                Philox4 w;
+                if constexpr (DMA) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w.w[e] = wq[k - 1][e];
+                } else {
+                    w = noise_block((size_t)wrap(zk, nz) * plane + xy, t0 + (uint64_t)(k - 1), a.seed);
+                }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     // FP64: n r with r = (w + 1/2) 2^-31 is the exact real
@@ -257,7 +340,8 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                 NtStore<S>::put(vn + off, ov);
             }
         }
-        __syncthreads(); // all reads of the staged planes are done
+        if constexpr (DMA) lds_barrier(); // all reads of the staged planes are done
+        else __syncthreads();
         // Stage the newest plane of levels 0..T-1 (the centre plane of the next iteration).
         if (has) {
 #pragma unroll
@@ -274,7 +358,12 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                     for (int e = 0; e < 4; ++e) lds_at(f, k, rys - k, e) = win[k][slot3(P - k + 1)][f][e];
             }
         }
-        __syncthreads();
+        if constexpr (DMA) {
+            make_noise(i + 1, full);
+            lds_barrier();
+        } else {
+            __syncthreads();
+        }
     };
 
     // The straight-line variant needs more registers; it is used where they
@@ -323,15 +412,25 @@ __global__ __launch_bounds__(NT, (tb_min_waves<S, T, NT>())) void stencil_tb(con
     const int z0 = bz * a.zc;
     const uint64_t t0 = NOISE ? step_index(a) : 0;
     const int ze = min(z0 + a.zc, a.nz);
-    // FP64 runs with dt = 1 (the workload of the paper) take the variant
-    // without the dt products.
-    if constexpr (sizeof(S) == 8) {
-        if (a.dt == 1.0) {
-            tb_tile<S, TXG, TY, T, NT, NOISE, false, true>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, ze, t0, lds);
-            return;
+    auto run = [&](uint4 *pre_lds) {
+        // FP64 runs with dt = 1 (the workload of the paper) take the variant
+        // without the dt products.
+        if constexpr (sizeof(S) == 8) {
+            if (a.dt == 1.0) {
+                tb_tile<S, TXG, TY, T, NT, NOISE, false, true>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, ze, t0,
+                                                               lds, pre_lds);
+                return;
+            }
         }
+        tb_tile<S, TXG, TY, T, NT, NOISE, false, false>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, ze, t0, lds,
+                                                        pre_lds);
+    };
+    if constexpr (tb_dma<S, T, NT, NOISE, false>()) {
+        __shared__ uint4 pre_lds[4 * NT];
+        run(pre_lds);
+    } else {
+        run(nullptr);
     }
-    tb_tile<S, TXG, TY, T, NT, NOISE, false, false>(u, v, un, vn, a, bx * (TXG * 4), by * TY, z0, ze, t0, lds);
 }
 
 // Persistent sweep over many independent simulations: each workgroup walks
@@ -365,12 +464,12 @@ __global__ __launch_bounds__(NT) void stencil_tb_batch(BatchArgs b)
         if constexpr (sizeof(S) == 8) {
             if (a.dt == 1.0) {
                 tb_tile<S, TXG, TY, T, NT, NOISE, true, true>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, ze,
-                                                              t0, lds);
+                                                              t0, lds, nullptr);
                 continue;
             }
         }
         tb_tile<S, TXG, TY, T, NT, NOISE, true, false>(u, v, un, vn, a, w.bx * (TXG * 4), w.by * TY, z0, ze, t0,
-                                                       lds);
+                                                       lds, nullptr);
     }
 }
 

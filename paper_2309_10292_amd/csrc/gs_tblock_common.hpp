@@ -1,6 +1,6 @@
-// Pieces shared by the temporally blocked kernels (gs_tblock.hip,
-// gs_tblock2.hip): the cell update of one level, non-temporal vector stores
-// of the output plane, and the compile-time plane-slot and phase helpers.
+// Pieces of the temporally blocked kernels (gs_tblock.hip): the cell update
+// of one level, non-temporal vector stores of the output plane, and the
+// compile-time plane-slot and phase helpers.
 #pragma once
 
 #include "gs_device.hpp"

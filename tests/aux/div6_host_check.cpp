@@ -41,6 +41,16 @@ int main()
         check(from_bits(m));
         check(-from_bits(m));
     }
+    // subnormal arguments across the whole significand range (strided), and
+    // the exact ties m = 6 j + 3 at every magnitude, both signs
+    for (uint64_t i = 0; i < (1u << 21); ++i) {
+        const uint64_t m = i * 2147483659ull % (1ull << 52);
+        const uint64_t j = (i * 6700417ull) % ((1ull << 52) / 6);
+        check(from_bits(m));
+        check(-from_bits(m));
+        check(from_bits(6 * j + 3));
+        check(-from_bits(6 * j + 3));
+    }
     // the normal arguments whose quotient is subnormal or just normal:
     // exponent fields 1..5, strided through the significand
     for (uint64_t e = 1; e <= 5; ++e)

@@ -41,21 +41,21 @@ def test_traffic_only_for_the_current_kernel_and_launch(tmp_path):
 
 def test_roofline_fraction_is_of_the_binding_roof():
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9   # 256 x 4 x 16 lanes x 2.4 GHz
-    assert bench.alu_ops_per_cell_update("f64", True) == 52
-    assert bench.alu_ops_per_cell_update("f64", False) == 39
+    assert bench.alu_ops_per_cell_update("f64", True) == 48
+    assert bench.alu_ops_per_cell_update("f64", False) == 35
     assert bench.alu_ops_per_cell_update("f32", True) is None
     cells = 512 ** 3
     # a T = 3 launch of 1.3 ms: one pass of 32 B per cell is 4.29e9 B
     r = bench.roofline("f64", True, cells, 3, 1.3, None)
     assert r["hbm"]["bytes_per_launch"] == 32 * cells
     assert abs(r["hbm"]["achieved"] - 32 * cells / 1.3e-3 / 1e9) < 0.1
-    assert abs(r["alu"]["achieved"] - 52 * 3 * cells / 1.3e-3 / 1e12) < 0.01
+    assert abs(r["alu"]["achieved"] - 48 * 3 * cells / 1.3e-3 / 1e12) < 0.01
     assert r["frac"] == max(r["hbm"]["frac"], r["alu"]["frac"]) <= 1.0
     assert r["bound"] == ("alu" if r["alu"]["frac"] > r["hbm"]["frac"] else "hbm")
     # the Eq. 5a-style figure counts every fused step and may exceed the peak
     assert abs(r["effective"]["gbs"] - 3 * 32 * cells / 1.3e-3 / 1e9) < 0.1
     # a launch at the binding roof's time gives frac 1
-    t_roof = max(32 * cells / 8e12, 52 * 3 * cells / (bench.VALU_PEAK_TOPS * 1e12)) * 1e3
+    t_roof = max(32 * cells / 8e12, 48 * 3 * cells / (bench.VALU_PEAK_TOPS * 1e12)) * 1e3
     assert abs(bench.roofline("f64", True, cells, 3, t_roof, None)["frac"] - 1.0) < 1e-3
     m = bench.roofline("f64", True, cells, 3, 1.3, 4.7e9)["measured"]
     assert abs(m["ratio_to_one_pass"] - 4.7e9 / (32 * cells)) < 1e-3

@@ -88,19 +88,21 @@ def _bits_equal(a, b):
     return np.array_equal(np.ascontiguousarray(a).view(np.uint64), np.ascontiguousarray(b).view(np.uint64))
 
 
-@pytest.mark.parametrize("Dv,dt", [(0.5, 1.0), (1.0, 0.9)])
-def test_fp64_subnormal_states_bitwise(torch, Dv, dt):
+@pytest.mark.parametrize("Dv,dt,noise", [(0.5, 1.0, 0.0), (1.0, 0.9, 0.0), (0.5, 1.0, 1e-200)])
+def test_fp64_subnormal_states_bitwise(torch, Dv, dt, noise):
     """FP64 from states whose v is subnormal (m 2^-1074, m < 2^20, the decayed
     tails of a field), with u = 0 and with u random, and from a state whose u
     is subnormal too, in the single-step kernel and the blocked kernel with one
     and three fused steps, bit for bit against the oracle. About one in twelve
     such Laplacian numerators is an odd multiple of 3 2^-1074, whose quotient
     by 6 is a tie of the subnormal grid that only the true division rounds to
-    even (Eq. 3 divides by 6)."""
+    even (Eq. 3 divides by 6). The case with noise (1e-200, added to u) runs
+    the noise kernels too, among them the three-step one that prefetches
+    through LDS."""
     from paper_2309_10292_amd import gs
     shape = (12, 20, 40)
     n = 7
-    p = dict(Du=0.2, Dv=Dv, F=0.02, k=0.048, dt=dt)
+    p = dict(Du=0.2, Dv=Dv, F=0.02, k=0.048, dt=dt, noise=noise, seed=31)
     tiles = [(1, 1)] + [(t, T) for t in gs.tblock_tiles() for T in (1, 3) if T <= gs.max_tblock(t, "f64")]
     v0 = subnormal_field(shape, seed=int(Dv * 10))
     u_rand, _ = random_state(shape, seed=5, lo_u=0.2, hi_u=1.0)
