@@ -245,10 +245,11 @@ gs_status check(gs_sim *s)
 // fuses three steps in the 512-lane 64 x 22 tile; with noise the other
 // storage types fuse two steps in the same tile (the Philox blocks of deeper
 // fusion cost more than the traffic they save); without noise FP32 fuses two
-// steps and the 16-bit types one in the 1024-lane tile. Smaller grids fuse
-// two steps: in 256-lane workgroups below 4 M cells (more workgroups for
-// 256 CUs), above that in the 768-lane tile for FP64 and the 512-lane one for
-// the others. The single-step kernel (tiles 1..4) runs when asked for.
+// steps in the 1024-lane tile and the 16-bit types two in the 512-lane one.
+// Smaller grids fuse two steps: in 256-lane workgroups below 4 M cells (more
+// workgroups for 256 CUs), above that in the 768-lane tile for FP64 and the
+// 512-lane one for the others. The single-step kernel (tiles 1..4) runs when
+// asked for.
 double grid_cells(const gs_params &p) { return (double)p.nx * p.ny * p.nz; }
 bool large_grid(const gs_params &p) { return grid_cells(p) >= 64.0 * 1024 * 1024; }
 
@@ -257,18 +258,15 @@ int default_tile(const gs_params &p)
     const int tb = gs::num_tiles(); // tiles tb + 1 .. tb + 5 are the blocked shapes 1..5
     if (grid_cells(p) < 4.0 * 1024 * 1024) return tb + 1;
     if (!large_grid(p)) return p.storage == GS_F64 ? tb + 4 : tb + 2;
-    if (p.storage == GS_F64 || p.noise != 0.0) return tb + 2;
-    return tb + 5;
+    if (p.storage == GS_F32 && p.noise == 0.0) return tb + 5;
+    return tb + 2;
 }
 
 int default_tblock(const gs_params &p, int tile)
 {
     if (tile <= gs::num_tiles()) return 1;
     int T = 2;
-    if (large_grid(p)) {
-        if (p.storage == GS_F64) T = 3;
-        else if (p.storage != GS_F32 && p.noise == 0.0) T = 1;
-    }
+    if (large_grid(p) && p.storage == GS_F64) T = 3;
     const int mt = tile_max_tblock(tile, p.storage);
     return T < mt ? T : mt;
 }

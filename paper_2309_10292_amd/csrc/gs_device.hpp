@@ -240,6 +240,29 @@ __device__ __forceinline__ float lap_comp_f32(float c, float xm, float xp, float
     return (s - k) * (1.0f / 6.0f);
 }
 
+// Laplacian in FP32 of values read from 2-byte storage: the six differences
+// summed in three levels without compensation. A difference of two 16-bit
+// values (for the complemented BF16 storage, of their complements) is exact
+// in FP32 whenever their exponents are within 16 of each other (a BF16 or
+// FP16 value has at most 11 significant bits), and the sum errs by at most
+// 3 u sum |d_i| (u = 2^-24): below 2e-7 of the differences, while the state
+// is rounded to 2^-9 (BF16) or 2^-12 (FP16) of itself after every step. The
+// compensated sum buys nothing at this storage and costs 16 more operations
+// per field.
+__device__ __forceinline__ float lap_sum_f32(float c, float xm, float xp, float ym, float yp, float zm, float zp)
+{
+    const float s = ((xm - c) + (xp - c)) + ((ym - c) + (yp - c)) + ((zm - c) + (zp - c));
+    return s * (1.0f / 6.0f);
+}
+// The FP32-arithmetic Laplacian of storage type S: compensated for FP32
+// storage, the plain sum for 2-byte storage.
+template <typename S>
+__device__ __forceinline__ float lap_f32(float c, float xm, float xp, float ym, float yp, float zm, float zp)
+{
+    if constexpr (sizeof(S) == 2) return lap_sum_f32(c, xm, xp, ym, yp, zm, zp);
+    else return lap_comp_f32(c, xm, xp, ym, yp, zm, zp);
+}
+
 // FP64 Laplacian in the canonical order: ((x- + x+) + (y- + y+)) + (z- + z+),
 // then (sum - 6 c) / 6.
 __host__ __device__ __forceinline__ double lap_f64(double c, double xm, double xp, double ym, double yp,

@@ -217,8 +217,8 @@ __global__ __launch_bounds__(256) void stencil_tile(const S *__restrict__ u, con
                     lu = lap_f64(uc, xm[0][i], xp[0][i], ym[0][i], yp[0][i], zm[0][i], zp[0][i]);
                     lv = lap_f64(vc, xm[1][i], xp[1][i], ym[1][i], yp[1][i], zm[1][i], zp[1][i]);
                 } else {
-                    lu = lap_comp_f32(uc, xm[0][i], xp[0][i], ym[0][i], yp[0][i], zm[0][i], zp[0][i]);
-                    lv = lap_comp_f32(vc, xm[1][i], xp[1][i], ym[1][i], yp[1][i], zm[1][i], zp[1][i]);
+                    lu = lap_f32<S>(uc, xm[0][i], xp[0][i], ym[0][i], yp[0][i], zm[0][i], zp[0][i]);
+                    lv = lap_f32<S>(vc, xm[1][i], xp[1][i], ym[1][i], yp[1][i], zm[1][i], zp[1][i]);
                 }
                 if constexpr (sizeof(C) == 4) {
                     // the FP32 sequence shared with the blocked kernels; r is n r

@@ -312,9 +312,9 @@ __device__ __forceinline__ void tb_tile(const S *__restrict__ u, const S *__rest
                     lu = lap_f64(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][sm][0][e], win[k - 1][sp][0][e]);
                     lv = lap_f64(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][sm][1][e], win[k - 1][sp][1][e]);
                 } else {
-                    lu = lap_comp_f32(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][sm][0][e],
+                    lu = lap_f32<S>(uc, xm[0][e], xp[0][e], ym[0][e], yp[0][e], win[k - 1][sm][0][e],
                                       win[k - 1][sp][0][e]);
-                    lv = lap_comp_f32(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][sm][1][e],
+                    lv = lap_f32<S>(vc, xm[1][e], xp[1][e], ym[1][e], yp[1][e], win[k - 1][sm][1][e],
                                       win[k - 1][sp][1][e]);
                 }
                 C uo, vo;
