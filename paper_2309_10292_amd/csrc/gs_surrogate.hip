@@ -503,15 +503,20 @@ int conv32p_zc(const Geo &g, int nsamp)
 //
 // The workgroups are persistent: each walks work items (a patch of 16 x-cells
 // by 4 y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
-// sums in registers. Per plane z of dz: the act plane z+1 enters an LDS ring
-// of three planes (6 rows x 16 cells per channel, in three copies shifted by
-// x - 1, x, x + 1 so that every B fragment is one aligned 16-byte read), and
-// dz's plane is staged channel-major; wave w then multiplies for the offsets
-// d = w, w + 4, ... (two K chunks of 32 cells each). Channel rows are padded
-// so that the 16 lanes of a fragment read hit distinct banks. The bias
-// gradient (the sum of dz over cells) is accumulated while dz is staged. Each
-// workgroup writes its partial sums (padded 16*MT x 16*NT per offset, and 32
-// bias sums) once.
+// sums in registers. The act planes sit in an LDS ring of three planes (6 rows
+// x 16 cells per channel, in three copies shifted by x - 1, x, x + 1 so that
+// every B fragment is one aligned 16-byte read), dz's plane is staged
+// channel-major, and wave w multiplies plane z for the offsets d = w, w + 4,
+// ... (two K chunks of 32 cells each). Channel rows are padded so that the 16
+// lanes of a fragment read hit distinct banks. Staging is software-pipelined:
+// before plane z is multiplied, the first lanes load act plane z + 2 (six
+// cells per row and channel group, once for all three copies) and the last
+// lanes load dz plane z + 1 into registers; after the barrier that ends plane
+// z they transpose them into LDS, so the loads' latency hides under the
+// MFMAs and the two kinds of staging run side by side. The bias gradient (the
+// sum of dz over cells) is accumulated while dz is staged. Each workgroup
+// writes its partial sums (padded 16*MT x 16*NT per offset, and 32 bias sums)
+// once.
 constexpr int WG_ZC = 16;
 
 template <int CIN, int COUTS, int MT, int NT>
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     constexpr int AS = 6 * 16 + 8;          // u16 per channel of one act copy (6 rows x 16 cells, padded)
     constexpr int DS = 64 + 8;              // u16 per channel of the dz plane (4 rows x 16 cells, padded)
     constexpr int NCG = CIN / 8, NCGZ = COUTS / 8;
-    constexpr int T_ACT = 3 * 6 * 4 * NCG;  // staging tasks of one act plane: copy x row x 4-cell group x 8 channels
+    constexpr int T_ACT = 6 * 4 * NCG;      // staging tasks of one act plane: row x 4-cell group x 8 channels
     constexpr int T_DZ = 4 * 4 * NCGZ;      // staging tasks of one dz plane
     static_assert(T_DZ <= 256, "one dz staging task per lane");
     __shared__ __align__(16) u16 act_l[9 * NCI * AS]; // [ring slot][copy][channel][row][cell]
@@ -584,60 +589,85 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         const int x0 = tx * 16, y0 = ty * 4, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
         const size_t sbase = (size_t)smp * g.ncell;
 
-        // act plane p (z0 - 1 <= p <= ze) into ring slot (p - z0 + 1) mod 3
-        auto stage_act = [&](int p) {
-            const int slot = (p - z0 + 1) % 3;
-            const int zp = wrapc(p, g.nz);
-            for (int t = tid; t < T_ACT; t += 256) {
-                const int cg = t % NCG;
-                int rest = t / NCG;
-                const int g4 = rest % 4;
-                rest /= 4;
-                const int rr = rest % 6;
-                const int sc = rest / 6;
+        // act plane p (z0 - 1 <= p <= ze) into ring slot (p - z0 + 1) mod 3:
+        // a task (one of the first T_ACT lanes) loads cells 4 g4 - 1 .. 4 g4 + 4
+        // of one row and channel group once, and writes the group's four
+        // cells into all three copies; the dz plane is staged by the last
+        // T_DZ lanes. Loads go out a plane ahead (into registers) and are
+        // written to LDS after the plane before has been multiplied.
+        static_assert(T_ACT + T_DZ <= 256, "one staging task per lane");
+        uint4 qa[6], qd[4];
+        auto load_act = [&](int p) {
+            if (tid < T_ACT) {
+                const int cg = tid % NCG;
+                const int g4 = (tid / NCG) % 4;
+                const int rr = tid / (4 * NCG);
                 const int y = wrapc(y0 + rr - 1, g.ny);
-                const size_t rowbase = sbase + ((size_t)zp * g.ny + y) * g.nx;
-                uint4 q[4];
+                const size_t rowbase = sbase + ((size_t)wrapc(p, g.nz) * g.ny + y) * g.nx;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int x = wrapc(x0 + 4 * g4 + k + sc - 1, g.nx);
-                    q[k] = *reinterpret_cast<const uint4 *>(a.act + (rowbase + x) * CIN + 8 * cg);
+                for (int k = 0; k < 6; ++k) {
+                    const int x = wrapc(x0 + 4 * g4 + k - 1, g.nx);
+                    qa[k] = *reinterpret_cast<const uint4 *>(a.act + (rowbase + x) * CIN + 8 * cg);
                 }
-                transpose_store(q, act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 4 * g4, AS);
+            }
+        };
+        auto store_act = [&](int p) {
+            if (tid < T_ACT) {
+                const int slot = (p - z0 + 1) % 3;
+                const int cg = tid % NCG;
+                const int g4 = (tid / NCG) % 4;
+                const int rr = tid / (4 * NCG);
+#pragma unroll
+                for (int sc = 0; sc < 3; ++sc) {
+                    const uint4 q[4] = {qa[sc], qa[sc + 1], qa[sc + 2], qa[sc + 3]};
+                    transpose_store(q, act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 4 * g4, AS);
+                }
             }
         };
         // dz plane z (rows past ny contribute zero)
-        auto stage_dz = [&](int z) {
-            if (tid < T_DZ) {
-                const int cg = tid % NCGZ;
-                const int g4 = (tid / NCGZ) % 4;
-                const int rr = tid / (4 * NCGZ);
-                const int y = y0 + rr;
-                uint4 q[4];
+        const int u = tid - (256 - T_DZ);
+        auto load_dz = [&](int z) {
+            if (u >= 0) {
+                const int cg = u % NCGZ;
+                const int g4 = (u / NCGZ) % 4;
+                const int y = y0 + u / (4 * NCGZ);
                 if (y < g.ny) {
                     const size_t base = sbase + ((size_t)z * g.ny + y) * g.nx + x0 + 4 * g4;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) q[k] = *reinterpret_cast<const uint4 *>(a.dz + (base + k) * COUTS + 8 * cg);
+                    for (int k = 0; k < 4; ++k) qd[k] = *reinterpret_cast<const uint4 *>(a.dz + (base + k) * COUTS + 8 * cg);
                 } else {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) q[k] = uint4{0u, 0u, 0u, 0u};
+                    for (int k = 0; k < 4; ++k) qd[k] = uint4{0u, 0u, 0u, 0u};
                 }
+            }
+        };
+        auto store_dz = [&]() {
+            if (u >= 0) {
+                const int cg = u % NCGZ;
+                const int g4 = (u / NCGZ) % 4;
+                const int rr = u / (4 * NCGZ);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(&q[k]);
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd[k]);
 #pragma unroll
                     for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
                 }
-                transpose_store(q, dz_l + (8 * cg) * DS + rr * 16 + 4 * g4, DS);
+                transpose_store(qd, dz_l + (8 * cg) * DS + rr * 16 + 4 * g4, DS);
             }
         };
 
-        stage_act(z0 - 1);
-        stage_act(z0);
+        load_act(z0 - 1);
+        store_act(z0 - 1);
+        load_act(z0);
+        store_act(z0);
+        load_act(z0 + 1);
+        load_dz(z0);
+        store_act(z0 + 1);
+        store_dz();
+        __syncthreads();
         for (int z = z0; z < ze; ++z) {
-            stage_act(z + 1);
-            stage_dz(z);
-            __syncthreads();
+            if (z + 2 <= ze) load_act(z + 2);
+            if (z + 1 < ze) load_dz(z + 1);
             bf16x8 af[2][MT];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
@@ -662,15 +692,18 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
                     }
                 }
             }
-            __syncthreads(); // the ring slot and the dz plane are rewritten next
+            __syncthreads(); // the ring slot of plane z - 1 and the dz plane are rewritten next
+            if (z + 2 <= ze) store_act(z + 2);
+            if (z + 1 < ze) store_dz();
+            __syncthreads();
         }
     }
 
-    // Bias partials: lane t < T_DZ summed channels 8 (t % NCGZ) + c; fold the
-    // lanes of each channel in lane order.
-    if (tid < T_DZ)
+    // Bias partials: dz staging task t (lane 256 - T_DZ + t) summed channels
+    // 8 (t % NCGZ) + c; fold the tasks of each channel in task order.
+    if (tid >= 256 - T_DZ)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) bsum_l[tid][c] = bs[c];
+        for (int c = 0; c < 8; ++c) bsum_l[tid - (256 - T_DZ)][c] = bs[c];
     __syncthreads();
     if (tid < COUTS) {
         float t = 0.f;
