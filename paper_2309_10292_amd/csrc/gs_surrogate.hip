@@ -509,14 +509,14 @@ int conv32p_zc(const Geo &g, int nsamp)
 // channel-major, and wave w multiplies plane z for the offsets d = w, w + 4,
 // ... (two K chunks of 32 cells each). Channel rows are padded so that the 16
 // lanes of a fragment read hit distinct banks. Staging is software-pipelined:
-// before plane z is multiplied, the first lanes load act plane z + 2 (six
-// cells per row and channel group, once for all three copies) and the last
-// lanes load dz plane z + 1 into registers; after the barrier that ends plane
-// z they transpose them into LDS, so the loads' latency hides under the
-// MFMAs and the two kinds of staging run side by side. The bias gradient (the
-// sum of dz over cells) is accumulated while dz is staged. Each workgroup
-// writes its partial sums (padded 16*MT x 16*NT per offset, and 32 bias sums)
-// once.
+// before plane z is multiplied, the first lanes load act plane z + 2 (per
+// lane a pair of cells and its two x-neighbours, of one row and channel
+// group, once for all three copies) and the last lanes load dz plane z + 1
+// into registers; after the barrier that ends plane z they transpose them
+// into LDS, so the loads' latency hides under the MFMAs and the two kinds of
+// staging run side by side. The bias gradient (the sum of dz over cells) is
+// accumulated while dz is staged. Each workgroup writes its partial sums
+// (padded 16*MT x 16*NT per offset, and 32 bias sums) once.
 constexpr int WG_ZC = 16;
 
 template <int CIN, int COUTS, int MT, int NT>
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     constexpr int AS = 6 * 16 + 8;          // u16 per channel of one act copy (6 rows x 16 cells, padded)
     constexpr int DS = 64 + 8;              // u16 per channel of the dz plane (4 rows x 16 cells, padded)
     constexpr int NCG = CIN / 8, NCGZ = COUTS / 8;
-    constexpr int T_ACT = 6 * 4 * NCG;      // staging tasks of one act plane: row x 4-cell group x 8 channels
+    constexpr int T_ACT = 6 * 8 * NCG;      // staging tasks of one act plane: row x 2-cell pair x 8 channels
     constexpr int T_DZ = 4 * 4 * NCGZ;      // staging tasks of one dz plane
     static_assert(T_DZ <= 256, "one dz staging task per lane");
     __shared__ __align__(16) u16 act_l[9 * NCI * AS]; // [ring slot][copy][channel][row][cell]
@@ -590,23 +590,23 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         const size_t sbase = (size_t)smp * g.ncell;
 
         // act plane p (z0 - 1 <= p <= ze) into ring slot (p - z0 + 1) mod 3:
-        // a task (one of the first T_ACT lanes) loads cells 4 g4 - 1 .. 4 g4 + 4
-        // of one row and channel group once, and writes the group's four
-        // cells into all three copies; the dz plane is staged by the last
-        // T_DZ lanes. Loads go out a plane ahead (into registers) and are
-        // written to LDS after the plane before has been multiplied.
+        // a task (one of the first T_ACT lanes) loads cells 2 h - 1 .. 2 h + 2
+        // of one row and channel group once, and writes the pair 2 h, 2 h + 1
+        // into all three copies; the dz plane is staged by the last T_DZ
+        // lanes. Loads go out a plane ahead (into registers) and are written
+        // to LDS after the plane before has been multiplied.
         static_assert(T_ACT + T_DZ <= 256, "one staging task per lane");
-        uint4 qa[6], qd[4];
+        uint4 qa[4], qd[4];
         auto load_act = [&](int p) {
             if (tid < T_ACT) {
                 const int cg = tid % NCG;
-                const int g4 = (tid / NCG) % 4;
-                const int rr = tid / (4 * NCG);
+                const int h = (tid / NCG) % 8;
+                const int rr = tid / (8 * NCG);
                 const int y = wrapc(y0 + rr - 1, g.ny);
                 const size_t rowbase = sbase + ((size_t)wrapc(p, g.nz) * g.ny + y) * g.nx;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const int x = wrapc(x0 + 4 * g4 + k - 1, g.nx);
+                for (int k = 0; k < 4; ++k) {
+                    const int x = wrapc(x0 + 2 * h + k - 1, g.nx);
                     qa[k] = *reinterpret_cast<const uint4 *>(a.act + (rowbase + x) * CIN + 8 * cg);
                 }
             }
@@ -615,12 +615,20 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
             if (tid < T_ACT) {
                 const int slot = (p - z0 + 1) % 3;
                 const int cg = tid % NCG;
-                const int g4 = (tid / NCG) % 4;
-                const int rr = tid / (4 * NCG);
+                const int h = (tid / NCG) % 8;
+                const int rr = tid / (8 * NCG);
 #pragma unroll
                 for (int sc = 0; sc < 3; ++sc) {
-                    const uint4 q[4] = {qa[sc], qa[sc + 1], qa[sc + 2], qa[sc + 3]};
-                    transpose_store(q, act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 4 * g4, AS);
+                    const uint32_t *w0 = reinterpret_cast<const uint32_t *>(&qa[sc]);
+                    const uint32_t *w1 = reinterpret_cast<const uint32_t *>(&qa[sc + 1]);
+                    u16 *dst = act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 2 * h;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int wi = c >> 1;
+                        const uint32_t o = (c & 1) ? (w0[wi] >> 16) | (w1[wi] & 0xffff0000u)
+                                                   : (w0[wi] & 0xffffu) | (w1[wi] << 16);
+                        *reinterpret_cast<uint32_t *>(dst + c * AS) = o;
+                    }
                 }
             }
         };
