@@ -360,6 +360,8 @@ gs_status gs_surrogate_adam(gs_surrogate *s, float lr, float beta1, float beta2,
  *                             row: (u_hi, v_hi, f, k, u_lo, v_lo, 0, 0), u and
  *                             v as the BF16 pairs that share one weight;
  *   GS_SURR_PRE (layer 0..2)  pre-activation z = conv + bias, BF16, 32 channels;
+ *                             loss_grad's forward pass only (a prediction
+ *                             stores no pre-activations: GS_ERR_STATE);
  *   GS_SURR_ACT (layer 0..2)  GELU of the FP32 pre-activation, BF16, 32 channels;
  *   GS_SURR_PRED (layer 3)    the FP32 prediction u then v (2 * rows floats);
  *                             loss_grad's forward pass only (predict writes the

@@ -64,6 +64,7 @@ __device__ __forceinline__ bf16x8 load8(const u16 *p)
 
 // ------------------------------------------------------------------ convolution
 // MODE_HIDDEN: z = acc + bias, writes z and GELU(z) (32 channels, BF16).
+// MODE_ACT:    the same, writing GELU(z) only (inference keeps no z).
 // MODE_OUT:    pred = residual input + acc + bias for output channels 0, 1.
 // MODE_DGRAD:  writes acc * GELU'(zprev) (the gradient of the layer below's
 //              pre-activation, 32 channels, BF16).
@@ -215,6 +216,12 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
                     aq.y = (uint32_t)ab[2] | ((uint32_t)ab[3] << 16);
                     *reinterpret_cast<uint2 *>(a.zout + r * 32 + co0) = zq;
                     *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) = aq;
+                } else if constexpr (MODE == MODE_ACT) {
+                    u16 ab[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) ab[j] = f2bf(gelu(acc[t][j] + a.bias[co0 + j]));
+                    *reinterpret_cast<uint2 *>(a.aout + r * 32 + co0) =
+                        uint2{(uint32_t)ab[0] | ((uint32_t)ab[1] << 16), (uint32_t)ab[2] | ((uint32_t)ab[3] << 16)};
                 } else if constexpr (MODE == MODE_OUT) {
                     if (quad == 0) {
                         // r = s * ncell + cell indexes the planar (sample, cell) fields
@@ -246,8 +253,9 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
     }
 }
 
-// 32 -> 32 convolutions of the forward hidden layer and the data gradient,
-// with every weight fragment in registers. A wavefront owns RW rows of 16
+// 32 -> 32 convolutions of the forward hidden layer (with or without the
+// pre-activation's store) and the data gradient, with every weight fragment
+// in registers. A wavefront owns RW rows of 16
 // cells and both 16-channel N tiles (four accumulator chains) of one sample
 // and marches through a chunk of z planes with a private LDS ring of four
 // input planes (rows y-1 .. y+RW, cells x-1 .. x+16, channel group major),
@@ -330,7 +338,7 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
     // Epilogue values: the lane's biases are read once (the compiler cannot
     // move their loads past the output stores).
     float bias_r[NT][4] = {};
-    if constexpr (MODE == MODE_HIDDEN) {
+    if constexpr (MODE == MODE_HIDDEN || MODE == MODE_ACT) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -390,6 +398,10 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
                         asm volatile("" : "+v"(zz), "+v"(gz));
                         e1[r][t][j] = f2bf(zz);
                         e2[r][t][j] = f2bf(gz);
+                    } else if constexpr (MODE == MODE_ACT) {
+                        float gz = gelu(accp[r][t][j] + bias_r[t][j]);
+                        asm volatile("" : "+v"(gz));
+                        e1[r][t][j] = f2bf(gz);
                     } else {
                         const uint32_t w = j < 2 ? zq[r][t].x : zq[r][t].y;
                         const float zp = bf2f((u16)((j & 1) ? (w >> 16) : (w & 0xffffu)));
@@ -447,6 +459,11 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
                         uint2{(uint32_t)e1[0] | ((uint32_t)e1[1] << 16), (uint32_t)e1[2] | ((uint32_t)e1[3] << 16)};
                     *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) =
                         uint2{(uint32_t)e2[0] | ((uint32_t)e2[1] << 16), (uint32_t)e2[2] | ((uint32_t)e2[3] << 16)};
+                } else if constexpr (MODE == MODE_ACT) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) e1[j] = f2bf(gelu(accp[r][t][j] + bias_r[t][j]));
+                    *reinterpret_cast<uint2 *>(a.aout + cell * 32 + co0) =
+                        uint2{(uint32_t)e1[0] | ((uint32_t)e1[1] << 16), (uint32_t)e1[2] | ((uint32_t)e1[3] << 16)};
                 } else {
                     const uint2 zq = *reinterpret_cast<const uint2 *>(a.zprev + cell * 32 + co0);
                     const float zp[4] = {bf2f((u16)(zq.x & 0xffffu)), bf2f((u16)(zq.x >> 16)),
@@ -895,6 +912,8 @@ hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a,
         if (nb == 0 || nb > 0x7fffffffu) return hipErrorInvalidConfiguration;
         if (mode == MODE_HIDDEN)
             hipLaunchKernelGGL(conv32p_kernel<MODE_HIDDEN>, dim3((unsigned)nb), dim3(64 * C32_WAVES), 0, st, b);
+        else if (mode == MODE_ACT)
+            hipLaunchKernelGGL(conv32p_kernel<MODE_ACT>, dim3((unsigned)nb), dim3(64 * C32_WAVES), 0, st, b);
         else
             hipLaunchKernelGGL(conv32p_kernel<MODE_DGRAD>, dim3((unsigned)nb), dim3(64 * C32_WAVES), 0, st, b);
         return hipGetLastError();
@@ -904,6 +923,7 @@ hipError_t launch_conv(int cin, int nt, int mode, int io_f64, const ConvArgs &a,
     const int grid = (int)blocks;
 #define GS_CONV(CI, N, M, IO) hipLaunchKernelGGL((conv_kernel<CI, N, M, IO>), dim3(grid), dim3(256), 0, st, a)
     if (cin == 8 && nt == 2 && mode == MODE_HIDDEN) GS_CONV(8, 2, MODE_HIDDEN, float);
+    else if (cin == 8 && nt == 2 && mode == MODE_ACT) GS_CONV(8, 2, MODE_ACT, float);
     else if (cin == 32 && nt == 1 && mode == MODE_OUT && io_f64) GS_CONV(32, 1, MODE_OUT, double);
     else if (cin == 32 && nt == 1 && mode == MODE_OUT) GS_CONV(32, 1, MODE_OUT, float);
     else if (cin == 8 && nt == 2 && mode == MODE_DGRAD) GS_CONV(8, 2, MODE_DGRAD, float);

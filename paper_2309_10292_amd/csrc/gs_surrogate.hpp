@@ -12,7 +12,7 @@ namespace nn {
 constexpr float F_CENTER = 0.035f, F_SCALE = 0.025f;
 constexpr float K_CENTER = 0.055f, K_SCALE = 0.015f;
 
-enum { MODE_HIDDEN = 0, MODE_OUT = 1, MODE_DGRAD = 2 };
+enum { MODE_HIDDEN = 0, MODE_OUT = 1, MODE_DGRAD = 2, MODE_ACT = 3 };
 
 struct Geo {
     int nx, ny, nz;
@@ -25,9 +25,9 @@ struct ConvArgs {
     int zc;                 // planes per workgroup chunk (the 32 -> 32 hidden and data-gradient kernels pick their own)
     const uint16_t *in;     // channels-last BF16 input (CIN channels)
     const uint16_t *wpack;  // packed BF16 weights (B fragments)
-    const float *bias;      // MODE_HIDDEN / MODE_OUT
+    const float *bias;      // MODE_HIDDEN / MODE_ACT / MODE_OUT
     uint16_t *zout;         // MODE_HIDDEN: pre-activation (32 channels)
-    uint16_t *aout;         // MODE_HIDDEN: activation; MODE_DGRAD: gradient (32 channels)
+    uint16_t *aout;         // MODE_HIDDEN / MODE_ACT: activation; MODE_DGRAD: gradient (32 channels)
     const uint16_t *zprev;  // MODE_DGRAD: pre-activation of the layer below
     const void *res_u, *res_v; // MODE_OUT: residual input (planar, sample-major)
     void *out_u, *out_v;       // MODE_OUT: prediction (planar)

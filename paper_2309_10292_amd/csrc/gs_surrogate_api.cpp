@@ -153,8 +153,11 @@ int conv_zc(const gs_surrogate *s, int nsamp)
     return zc < s->geo.nz ? zc : s->geo.nz;
 }
 
-// Forward pass of nsamp samples; keeps pre-activations and activations.
-hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, const void *v, void *uo, void *vo)
+// Forward pass of nsamp samples; keeps the activations, and the
+// pre-activations too when keep_pre (the backward pass needs them; a
+// prediction does not, and skips their stores).
+hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, const void *v, void *uo, void *vo,
+                   bool keep_pre)
 {
     using namespace gs::nn;
     hipError_t e = launch_pack_input(io_f64, u, v, at<float>(s, s->L.fk), nsamp, s->geo.ncell,
@@ -169,9 +172,9 @@ hipError_t forward(gs_surrogate *s, int32_t nsamp, int io_f64, const void *u, co
         a.in = in;
         a.wpack = at<uint16_t>(s, s->L.wf[l]);
         a.bias = P + b_off(l);
-        a.zout = at<uint16_t>(s, s->L.z[l]);
+        a.zout = keep_pre ? at<uint16_t>(s, s->L.z[l]) : nullptr;
         a.aout = at<uint16_t>(s, s->L.a[l]);
-        e = launch_conv(k_cins[l], 2, MODE_HIDDEN, 0, a, s->stream);
+        e = launch_conv(k_cins[l], 2, keep_pre ? MODE_HIDDEN : MODE_ACT, 0, a, s->stream);
         in = a.aout;
     }
     if (e == hipSuccess) {
@@ -273,7 +276,7 @@ gs_status gs_surrogate_predict(gs_surrogate *s, int32_t nsamp, int32_t io_storag
     if (!u || !v || !u_out || !v_out || !F || !k) return fail(GS_ERR_INVALID_ARG, "NULL pointer");
     if (u_out == u || v_out == v || u_out == v || v_out == u) return fail(GS_ERR_INVALID_ARG, "outputs must not alias inputs");
     if ((st = upload_fk(s, nsamp, F, k)) != GS_OK) return st;
-    hipError_t e = forward(s, nsamp, io_storage == GS_F64, u, v, u_out, v_out);
+    hipError_t e = forward(s, nsamp, io_storage == GS_F64, u, v, u_out, v_out, false);
     if (e != hipSuccess) return hip_fail(e, "surrogate forward");
     s->last_fwd = nsamp;
     s->last_fwd_loss = false; // the stored data gradients no longer match the activations
@@ -292,7 +295,7 @@ gs_status gs_surrogate_loss_grad(gs_surrogate *s, int32_t nsamp, const float *u,
     if ((st = upload_fk(s, nsamp, F, k)) != GS_OK) return st;
     const size_t rows = (size_t)nsamp * s->geo.ncell;
     float *pu = at<float>(s, s->L.pu), *pv = at<float>(s, s->L.pv);
-    hipError_t e = forward(s, nsamp, 0, u, v, pu, pv);
+    hipError_t e = forward(s, nsamp, 0, u, v, pu, pv, true);
     const double n_terms = 2.0 * (double)rows;
     uint16_t *dz4 = at<uint16_t>(s, s->L.dz4);
     if (e == hipSuccess)
@@ -377,6 +380,8 @@ gs_status gs_surrogate_read_tensor(gs_surrogate *s, int32_t tensor, int32_t laye
     case GS_SURR_PRE:
     case GS_SURR_ACT:
         if (layer < 0 || layer > 2) return fail(GS_ERR_INVALID_ARG, "hidden layer %d outside [0, 2]", layer);
+        if (tensor == GS_SURR_PRE && s->last_fwd && !s->last_fwd_loss)
+            return fail(GS_ERR_STATE, "a prediction keeps no pre-activations: call gs_surrogate_loss_grad first");
         off = tensor == GS_SURR_PRE ? s->L.z[layer] : s->L.a[layer], bytes = rows * 32 * 2;
         break;
     case GS_SURR_PRED:
