@@ -134,6 +134,16 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
     }
     __syncthreads();
 
+    // One output-channel tile with 32 input channels (the output layer): its
+    // 27 weight fragments stay in registers, so the K loop reads only the
+    // activation fragments from LDS.
+    constexpr bool WREG = CIN == 32 && NT == 1;
+    bf16x8 wreg[WREG ? 27 : 1];
+    if constexpr (WREG) {
+#pragma unroll
+        for (int c = 0; c < 27; ++c) wreg[c] = __builtin_bit_cast(bf16x8, wl[c * 64 + lane]);
+    }
+
     const int yrow = y0 + wave;
     const bool row_ok = yrow < g.ny;
     for (int z = z0; z < ze; ++z) {
@@ -160,8 +170,10 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
                 const int dz = c / 9, dy = (c / 3) % 3, dx = c % 3;
                 const uint4 *rs = ring + ((z + dz + 2) % 3) * PLANE_V; // slot of plane z + dz - 1
                 avr[sl] = __builtin_bit_cast(bf16x8, rs[quad * GCELLS + (wave + dy) * RX + col + dx]);
+                if constexpr (!WREG) {
 #pragma unroll
-                for (int t = 0; t < NT; ++t) wvr[sl][t] = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                    for (int t = 0; t < NT; ++t) wvr[sl][t] = __builtin_bit_cast(bf16x8, wl[(c * NT + t) * 64 + lane]);
+                }
             };
 #pragma unroll
             for (int c = 0; c < KD; ++c) load(c, c);
@@ -169,7 +181,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
             for (int c = 0; c < 27; ++c) {
                 const int sl = c % KD;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvr[sl][t], avr[sl], acc[t], 0, 0, 0);
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(WREG ? wreg[c] : wvr[sl][t], avr[sl], acc[t], 0, 0, 0);
                 if (c + KD < 27) load(c + KD, sl);
                 // keep the reads KD chunks ahead of their MFMAs
                 __builtin_amdgcn_sched_barrier(0);
