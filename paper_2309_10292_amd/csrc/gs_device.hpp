@@ -219,27 +219,6 @@ template <typename S> __device__ __forceinline__ S fstore(int f, typename Traits
     else return Traits<S>::store(c);
 }
 
-// Laplacian in FP32 from the differences d_i = n_i - c (exact when a
-// neighbour is within a factor 2 of c), summed in the order x-, x+, y-, y+,
-// z-, z+ with Kahan's compensation: the correction k carries the rounding
-// error of each addition into the next one, and the sum is corrected by the
-// last k. The error is below (2u + O(u^2)) sum |d_i| (u = 2^-24), four
-// operations per added term.
-__device__ __forceinline__ float lap_comp_f32(float c, float xm, float xp, float ym, float yp,
-                                              float zm, float zp)
-{
-    const float d[6] = {xm - c, xp - c, ym - c, yp - c, zm - c, zp - c};
-    float s = d[0], k = 0.0f;
-#pragma unroll
-    for (int i = 1; i < 6; ++i) {
-        const float y = d[i] - k;
-        const float t = s + y;
-        k = (t - s) - y;
-        s = t;
-    }
-    return (s - k) * (1.0f / 6.0f);
-}
-
 // Laplacian in FP32 of values read from 2-byte storage: the six differences
 // summed in three levels without compensation. A difference of two 16-bit
 // values (for the complemented BF16 storage, of their complements) is exact
@@ -254,13 +233,25 @@ __device__ __forceinline__ float lap_sum_f32(float c, float xm, float xp, float 
     const float s = ((xm - c) + (xp - c)) + ((ym - c) + (yp - c)) + ((zm - c) + (zp - c));
     return s * (1.0f / 6.0f);
 }
-// The FP32-arithmetic Laplacian of storage type S: compensated for FP32
+// Laplacian in FP32 of values read from FP32 storage: the six FP32
+// differences (exact where a neighbour is within a factor 2 of c) summed in
+// FP64, which errs by at most 3 2^-53 sum |d_i|, then rounded once to FP32
+// and scaled. A compensated FP32 sum (Kahan) errs by up to (2u + O(u^2))
+// sum |d_i| (u = 2^-24), which exceeds a rounding of the sum itself wherever
+// the differences cancel, and takes more operations.
+__device__ __forceinline__ float lap_wide_f32(float c, float xm, float xp, float ym, float yp, float zm, float zp)
+{
+    const double s = (((double)(xm - c) + (double)(xp - c)) + ((double)(ym - c) + (double)(yp - c))) +
+                     ((double)(zm - c) + (double)(zp - c));
+    return (float)s * (1.0f / 6.0f);
+}
+// The FP32-arithmetic Laplacian of storage type S: the FP64 sum for FP32
 // storage, the plain sum for 2-byte storage.
 template <typename S>
 __device__ __forceinline__ float lap_f32(float c, float xm, float xp, float ym, float yp, float zm, float zp)
 {
     if constexpr (sizeof(S) == 2) return lap_sum_f32(c, xm, xp, ym, yp, zm, zp);
-    else return lap_comp_f32(c, xm, xp, ym, yp, zm, zp);
+    else return lap_wide_f32(c, xm, xp, ym, yp, zm, zp);
 }
 
 // FP64 Laplacian in the canonical order: ((x- + x+) + (y- + y+)) + (z- + z+),

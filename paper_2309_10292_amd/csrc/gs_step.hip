@@ -17,7 +17,8 @@
 // FP64 storage evaluates exactly the operation sequence of the FP64 definition
 // (pairwise neighbour sum, (s - 6c) / 6, source terms left to right, no
 // contraction), so results are bitwise equal to it. Other storage types
-// compute in FP32 with the compensated Laplacian and round on store.
+// compute in FP32 (the Laplacian's sum in FP64 for FP32 storage, plain for
+// 2-byte storage) and round on store.
 #include "gs_device.hpp"
 #include "gs_launch.hpp"
 

@@ -12,8 +12,8 @@ diagnostics' sums).
 
 Bars per field (max-abs over all cells; RMS over the cells that move): FP64
 bitwise; FP32 max 1e-5, RMS 1e-7; FP16 max 5e-2, RMS 5e-4; BF16 max 5e-1, RMS 5e-3.
-FP32 arithmetic with the compensated Laplacian adds about one FP32 rounding
-(6e-8) per step to values of order 1. 16-bit storage rounds every stored value
+FP32 arithmetic (the Laplacian's six differences summed in FP64) adds about one
+FP32 rounding (6e-8) per step to values of order 1. 16-bit storage rounds every stored value
 (half a unit in the last place of u ~ 1 is 2.4e-4 in FP16 and 2e-3 in BF16), and
 updates below that are lost; the Gray-Scott fronts of this workload amplify such
 perturbations over 200 steps, so the worst cell is tens of units off while the

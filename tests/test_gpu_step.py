@@ -242,7 +242,7 @@ def test_diagnostics_vs_oracle(torch, small_ref):
 
 
 def test_reduced_precision_within_bars(torch, small_ref):
-    """FP32 / FP16 / BF16 storage (FP32 arithmetic, compensated Laplacian) on
+    """FP32 / FP16 / BF16 storage (FP32 arithmetic) on
     the L=64 workload, 100 steps, against the FP64 oracle."""
     bars = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2, "bf16c": 5e-2}
     p = workload("small_l64")
