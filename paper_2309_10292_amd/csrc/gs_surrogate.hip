@@ -267,25 +267,28 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a)
 }
 
 // 32 -> 32 convolutions of the forward hidden layer (with or without the
-// pre-activation's store) and the data gradient, with every weight fragment
-// in registers. A wavefront owns RW rows of 16
-// cells and both 16-channel N tiles (four accumulator chains) of one sample
-// and marches through a chunk of z planes with a private LDS ring of four
-// input planes (rows y-1 .. y+RW, cells x-1 .. x+16, channel group major),
-// so the wavefronts of a workgroup never wait for each other. The K loop
-// reads only activation fragments from LDS, one per row and K chunk for two
-// MFMAs. Plane z's MFMAs and plane z-1's epilogue (bias, GELU or its
-// derivative, BF16 rounding) sit in one basic block, so the vector units
-// work while the matrix cores run. The MFMAs accumulate each output over the
-// 27 K chunks in the same order as conv_kernel, so the results are the same
-// bit for bit.
-constexpr int C32_RW = 2, C32_WAVES = 4;
+// pre-activation's store) and the data gradient. A wavefront owns RW rows of
+// 16 cells and both 16-channel N tiles (four accumulator chains) of one
+// sample and marches through a chunk of z planes with a private LDS ring of
+// three input planes (rows y-1 .. y+RW, cells x-1 .. x+16, channel group
+// major), so the wavefronts of a workgroup meet at one barrier only, after
+// the weights are staged. The weight fragments of the first C32_CR K chunks
+// sit in registers and the other chunks' in LDS (shared by the workgroup's
+// eight wavefronts), which leaves room for two wavefronts per SIMD: one
+// wavefront's vector work (the epilogue, the staging) then runs beside the
+// other's MFMAs. The K loop reads the activation fragments (one per row and
+// K chunk for two MFMAs) and the LDS weight fragments a few chunks ahead.
+// Plane z's MFMAs and plane z-1's epilogue (bias, GELU or its derivative,
+// BF16 rounding) sit in one basic block. The MFMAs accumulate each output
+// over the 27 K chunks in the same order as conv_kernel, so the results are
+// the same bit for bit.
+constexpr int C32_RW = 2, C32_WAVES = 8, C32_CR = 8;
 typedef unsigned u32x4 __attribute__((ext_vector_type(4))); // a native vector (no struct copies)
 template <bool B> struct BoolC {
     static constexpr bool value = B;
 };
 template <int MODE>
-__global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void conv32p_kernel(ConvArgs a)
+__global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(2, 2))) void conv32p_kernel(ConvArgs a)
 {
     constexpr int NT = 2, NCH = 27, VPC = 4, RW = C32_RW, PYW = RW * C32_WAVES;
     constexpr int RCELLS = RX * (RW + 2);              // ring cells per plane
@@ -293,20 +296,25 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
     constexpr int SLOT_V = GC * VPC;                   // 16-byte vectors per plane slot
     constexpr int LOAD_V = RCELLS * VPC;               // vectors loaded per plane
     constexpr int LOADS = (LOAD_V + 63) / 64;
-    __shared__ u32x4 ring_all[C32_WAVES * 4 * SLOT_V];
+    constexpr int CR = C32_CR, CL = NCH - CR;          // weight chunks in registers / in LDS
+    __shared__ u32x4 ring_all[C32_WAVES * 3 * SLOT_V];
+    __shared__ uint4 wl[CL * NT * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    u32x4 *ring = ring_all + wave * 4 * SLOT_V;
+    u32x4 *ring = ring_all + wave * 3 * SLOT_V;
+    auto slot3 = [](int z) { return ((z % 3) + 3) % 3; };
     const int col = lane & 15, quad = lane >> 4;
     const Geo g = a.geo;
 
-    bf16x8 wr[NCH][NT];
+    bf16x8 wr[CR][NT];
     {
         const uint4 *wg = reinterpret_cast<const uint4 *>(a.wpack);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
+        for (int c = 0; c < CR; ++c)
 #pragma unroll
             for (int t = 0; t < NT; ++t) wr[c][t] = __builtin_bit_cast(bf16x8, wg[(c * NT + t) * 64 + lane]);
+        for (int i = threadIdx.x; i < CL * NT * 64; i += 64 * C32_WAVES) wl[i] = wg[CR * NT * 64 + i];
     }
+    __syncthreads();
     const int tx = g.nx / PX, ty = (g.ny + PYW - 1) / PYW, tzc = (g.nz + a.zc - 1) / a.zc;
     int b = blockIdx.x;
     const int bx = b % tx;
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
     const int s = b / tzc;
     const int x0 = bx * PX, yw = by * PYW + RW * wave, z0 = bz * a.zc;
     const int ze = min(z0 + a.zc, g.nz);
-    if (yw >= g.ny) return; // a wavefront below the grid (no barriers in this kernel)
+    if (yw >= g.ny) return; // a wavefront below the grid (no barriers after this point)
     const size_t sbase = (size_t)s * g.ncell, plane = (size_t)g.nx * g.ny;
 
     // This lane's ring vectors: offset within an input plane (in channels)
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
         for (int l = 0; l < LOADS; ++l) o[l] = *reinterpret_cast<const u32x4 *>(base + goff[l]);
     };
     auto stage_plane = [&](int z, const u32x4 (&o)[LOADS]) __attribute__((always_inline)) {
-        u32x4 *dst = ring + (z & 3) * SLOT_V;
+        u32x4 *dst = ring + slot3(z) * SLOT_V;
 #pragma unroll
         for (int l = 0; l < LOADS; ++l) dst[rpos[l]] = o[l];
     };
@@ -381,12 +389,16 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
         constexpr int KD = 3;
-        bf16x8 av[KD][RW];
+        bf16x8 av[KD][RW], wv[KD][NT];
         auto frag = [&](int c, int sl) __attribute__((always_inline)) {
             const int dz = c / 9, dy = (c / 3) % 3, dx = c % 3;
-            const u32x4 *rs = ring + ((z + dz - 1) & 3) * SLOT_V + quad * GC;
+            const u32x4 *rs = ring + slot3(z + dz - 1) * SLOT_V + quad * GC;
 #pragma unroll
             for (int r = 0; r < RW; ++r) av[sl][r] = __builtin_bit_cast(bf16x8, rs[(r + dy) * RX + col + dx]);
+            if (c >= CR) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) wv[sl][t] = __builtin_bit_cast(bf16x8, wl[((c - CR) * NT + t) * 64 + lane]);
+            }
         };
 #pragma unroll
         for (int c = 0; c < KD; ++c) frag(c, c);
@@ -398,7 +410,8 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
             for (int t = 0; t < NT; ++t)
 #pragma unroll
                 for (int r = 0; r < RW; ++r)
-                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[c][t], av[sl][r], acc[r][t], 0, 0, 0);
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c < CR ? wr[c < CR ? c : 0][t] : wv[sl][t], av[sl][r],
+                                                                        acc[r][t], 0, 0, 0);
             if (c + KD < NCH) frag(c + KD, sl);
             if constexpr (PREV) {
                 if (c < RW * NT * 4) {
@@ -512,10 +525,10 @@ __global__ __launch_bounds__(64 * C32_WAVES) __attribute__((amdgpu_waves_per_eu(
         last_epilogue(ze - 1, accA);
     }
 }
-// Planes per workgroup of conv32p_kernel: one workgroup of four wavefronts
-// fills a CU (its registers), so the chunk is the longest that still gives at
-// least two workgroups per CU, which amortises the weights' load and the ring's
-// first planes.
+// Planes per workgroup of conv32p_kernel: one workgroup of eight wavefronts
+// fills a CU (its registers and LDS), so the chunk is the longest that still
+// gives at least two workgroups per CU, which amortises the weights' load and
+// the ring's first planes.
 int conv32p_zc(const Geo &g, int nsamp)
 {
     const size_t cols = (size_t)(g.nx / PX) * ((g.ny + C32_RW * C32_WAVES - 1) / (C32_RW * C32_WAVES)) * (size_t)nsamp;
