@@ -386,7 +386,7 @@ hipError_t enqueue_steps(gs_sim *s, int64_t n, hipStream_t st, const uint64_t *t
 
 void drop_graph(gs_sim *s)
 {
-    if (s->graph.exec) hipGraphExecDestroy(s->graph.exec);
+    if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
     s->graph = GraphCache();
 }
 
@@ -558,7 +558,7 @@ gs_status gs_destroy(gs_sim *s)
     if (st != GS_OK) return st;
     hipError_t e = hipStreamSynchronize(s->stream);
     drop_graph(s);
-    if (s->capture_stream) hipStreamDestroy(s->capture_stream);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     s->magic = 0;
     delete s;
     if (e != hipSuccess) return hip_fail(e, "gs_destroy sync");
@@ -600,7 +600,7 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
+        if (e0) (void)hipEventDestroy(e0);
         return hip_fail(e, "gs_tune events");
     }
     const int save_tile = s->tile, save_tb = s->tblock, save_zc = s->zc;
@@ -649,8 +649,8 @@ gs_status gs_tune(gs_sim *s, int32_t reps, gs_tune_entry *table, int32_t capacit
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) {
         s->tile = save_tile;
         s->tblock = save_tb;
@@ -691,12 +691,12 @@ gs_status gs_step_graph(gs_sim *s, int64_t n_steps)
         hipError_t le = enqueue_steps(s, n_steps, s->capture_stream, t_dev, &par);
         e = hipStreamEndCapture(s->capture_stream, &graph);
         if (le != hipSuccess) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return hip_fail(le, "capture launches");
         }
         if (e != hipSuccess) return hip_fail(e, "end capture");
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) {
             g = GraphCache();
             return hip_fail(e, "graph instantiate");
@@ -768,7 +768,7 @@ gs_status gs_laplacian7(const double *f, double *out, int32_t nx, int32_t ny, in
     if (!aligned(f, 256) || !aligned(out, 256)) return fail(GS_ERR_INVALID_ARG, "pointers must be 256-byte aligned");
     if (f == out) return fail(GS_ERR_INVALID_ARG, "in-place Laplacian is not supported");
     if (nx < 4 || ny < 4 || nz < 4 || nx % 8 != 0)
-        return fail(GS_ERR_UNSUPPORTED, "grid %dx%dx%d unsupported (>= 4 each, nx % 8 == 0)", nx, ny, nz);
+        return fail(GS_ERR_UNSUPPORTED, "grid %dx%dx%d unsupported (>= 4 each, nx %% 8 == 0)", nx, ny, nz);
     hipError_t e = gs::launch_laplacian7(f, out, nx, ny, nz, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "laplacian launch");
     return GS_OK;

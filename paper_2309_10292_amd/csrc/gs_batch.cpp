@@ -125,7 +125,7 @@ gs::StepArgs shared_coef(const gs_batch *b)
 
 void drop_graph(gs_batch *b)
 {
-    if (b->graph.exec) hipGraphExecDestroy(b->graph.exec);
+    if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
     b->graph = BGraph();
 }
 
@@ -490,12 +490,12 @@ gs_status gs_batch_step_graph(gs_batch *b, int64_t n_steps)
         hipError_t le = enqueue_batch(b, n_steps, b->capture_stream, t_dev, cpar);
         e = hipStreamEndCapture(b->capture_stream, &graph);
         if (le != hipSuccess) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return hip_fail(le, "capture launches");
         }
         if (e != hipSuccess) return hip_fail(e, "end capture");
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (e != hipSuccess) {
             g = BGraph();
             return hip_fail(e, "graph instantiate");
@@ -544,7 +544,7 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
+        if (e0) (void)hipEventDestroy(e0);
         return hip_fail(e, "tune events");
     }
     std::vector<gs::SimDesc> desc = b->h_desc;
@@ -637,8 +637,8 @@ gs_status gs_batch_tune(gs_batch *b, int32_t reps, gs_batch_tune_entry *table, i
             t.gcells = cells / (best * 1e-3) / 1e9;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "gs_batch_tune");
     if (n_entries) *n_entries = (int32_t)classes.size();
     (void)count;
@@ -733,7 +733,7 @@ gs_status gs_batch_destroy(gs_batch *b)
     if (st != GS_OK) return st;
     hipError_t e = hipStreamSynchronize(b->stream);
     drop_graph(b);
-    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     b->magic = 0;
     delete b;
     return e == hipSuccess ? GS_OK : hip_fail(e, "gs_batch_destroy sync");

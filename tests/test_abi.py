@@ -119,6 +119,7 @@ def test_calibration_entry_points_validate():
     L = gs.load()
     assert L.gs_laplacian7(None, None, 64, 64, 64, None) == gs.GS_ERR_INVALID_ARG
     assert L.gs_laplacian7(4096, 8192, 60, 64, 64, None) == gs.GS_ERR_UNSUPPORTED
+    assert gs.last_error() == "grid 60x64x64 unsupported (>= 4 each, nx % 8 == 0)"
     assert L.gs_laplacian7(4096, 4096, 64, 64, 64, None) == gs.GS_ERR_INVALID_ARG
     assert L.gs_copy(4096, 8192, 17, None) == gs.GS_ERR_INVALID_ARG
     assert L.gs_copy(None, 8192, 16, None) == gs.GS_ERR_INVALID_ARG
