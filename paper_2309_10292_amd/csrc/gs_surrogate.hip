@@ -539,85 +539,104 @@ int conv32p_zc(const Geo &g, int nsamp)
 }
 
 // ------------------------------------------------------------------ weight gradient
-// dW[d][co][ci] = sum over cells of dz[cell][co] * act[neighbour(cell, d)][ci].
-// A = dz^T (rows co, K = cells), B = act (K = cells, columns ci): both MFMA
-// operands need 8 consecutive cells of one channel per lane, while memory is
-// channels-last, so the operands are transposed on their way into LDS.
+// dW[d][co][ci] = sum over cells of dz[cell][co] * act[cell + d][ci]: for each
+// of the 27 offsets d a product A B with A = dz^T (rows co, K = cells) and
+// B = act shifted by d (K = cells, columns ci), on 16x16x32 MFMAs whose K runs
+// over 32 cells (two rows of 16).
 //
 // The workgroups are persistent: each walks work items (a patch of 16 x-cells
 // by 4 y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
-// sums in registers. The act planes sit in an LDS ring of three planes (6 rows
-// x 16 cells per channel, in three copies shifted by x - 1, x, x + 1 so that
-// every B fragment is one aligned 16-byte read), dz's plane is staged
-// channel-major, and wave w multiplies plane z for the offsets d = w, w + 4,
-// ... (two K chunks of 32 cells each). Channel rows are padded so that the 16
-// lanes of a fragment read hit distinct banks. Staging is software-pipelined:
-// before plane z is multiplied, the first lanes load act plane z + 2 (per
-// lane a pair of cells and its two x-neighbours, of one row and channel
-// group, once for all three copies) and the last lanes load dz plane z + 1
-// into registers; after the barrier that ends plane z they transpose them
-// into LDS, so the loads' latency hides under the MFMAs and the two kinds of
-// staging run side by side. The bias gradient (the sum of dz over cells) is
-// accumulated while dz is staged. Each workgroup writes its partial sums
-// (padded 16*MT x 16*NT per offset, and 32 bias sums) once.
-constexpr int WG_ZC = 16;
+// sums in registers. Act plane p meets dz planes p + 1, p and p - 1 (z offsets
+// -1, 0, +1), so the loop runs over act planes: while plane p is in LDS, the dz
+// fragments of the three planes it meets are held in registers, and every B
+// fragment read from LDS feeds three MFMAs, one per z offset (a third of the
+// LDS reads of a loop that takes the offsets one by one). For each offset the
+// planes are still added in increasing z. Both operands stay channels-last in
+// LDS, as in memory (16-byte chunks, no transposes on the way in): a fragment
+// (8 cells of one channel per lane) is two transposing LDS reads. Cells 8 .. 15
+// of every 16 have their channel halves swapped (rows of 32 channels) or are
+// moved 4 cells over (rows of 16), so that the two 16-lane groups of a
+// half-wave read distinct banks.
+//
+// Wave w owns one 16 x 16 output tile (co x ci) for all 27 offsets: with
+// four tiles (32 -> 32) for both K chunks of a plane, with two tiles two waves
+// share a tile, split the K chunks, and add their sums at the end. Staging is
+// double-buffered with one barrier per plane: act plane p + 2 and dz plane
+// p + 3 are loaded into registers while plane p is multiplied and stored into
+// the free buffers at the start of the next plane. The bias gradient (the sum
+// of dz over cells) is accumulated while dz is staged. Each workgroup writes
+// its partial sums (padded 16*MT x 16*NT per offset, and 32 bias sums) once.
+constexpr int WG_ZC = 64;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// Offset (16-bit units) of channel ch of cell `cell` in an LDS row of
+// channels-last cells of NC channels, with the bank swizzle described above.
+template <int NC>
+__device__ __forceinline__ int wg_pos(int cell, int ch)
+{
+    static_assert(NC == 16 || NC == 32, "rows of 16 or 32 channels");
+    if constexpr (NC == 32)
+        return cell * 32 + (ch ^ ((cell & 8) << 1));
+    else
+        return (cell ^ ((cell >> 1) & 4)) * 16 + ch;
+}
+
+// MFMA operand of cells cell0 .. cell0 + 7 and channels c0 .. c0 + 15 (one per
+// lane of a 16-lane group) from an LDS row. In each group of 16 lanes the
+// transposing read concatenates the 8-byte pieces the lanes address, in lane
+// order, into 64 values X and hands lane t the values X[t], X[t + 16],
+// X[t + 32] and X[t + 48]; so lane L addresses cell L / 4 (then 4 + L / 4)
+// at channels c0 + 4 (L % 4) .. + 3, and receives channel c0 + L of the
+// 8 cells.
+template <int NC>
+__device__ __forceinline__ bf16x8 frag_tr(const u16 *row, int cell0, int c0, int lane16)
+{
+    const int cell = cell0 + (lane16 >> 2), ch = c0 + 4 * (lane16 & 3);
+    typedef __attribute__((address_space(3))) v4s *lds_v4s;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(row + wg_pos<NC>(cell, ch)));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(row + wg_pos<NC>(cell + 4, ch)));
+    const v4s v[2] = {lo, hi};
+    return __builtin_bit_cast(bf16x8, v);
+}
 
 template <int CIN, int COUTS, int MT, int NT>
-__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void wgrad_kernel(WgradArgs a)
 {
-    constexpr int ND = 7;                   // ceil(27 / 4) offsets per wave
     constexpr int NCI = 16 * NT, NCO = 16 * MT;
-    constexpr int AS = 6 * 16 + 8;          // u16 per channel of one act copy (6 rows x 16 cells, padded)
-    constexpr int DS = 64 + 8;              // u16 per channel of the dz plane (4 rows x 16 cells, padded)
     constexpr int NCG = CIN / 8, NCGZ = COUTS / 8;
-    constexpr int T_ACT = 6 * 8 * NCG;      // staging tasks of one act plane: row x 2-cell pair x 8 channels
-    constexpr int T_DZ = 4 * 4 * NCGZ;      // staging tasks of one dz plane
-    static_assert(T_DZ <= 256, "one dz staging task per lane");
-    __shared__ __align__(16) u16 act_l[9 * NCI * AS]; // [ring slot][copy][channel][row][cell]
-    __shared__ __align__(16) u16 dz_l[NCO * DS];      // [channel][row * 16 + cell]
+    constexpr int KS = MT * NT == 4 ? 1 : 2; // waves per output tile (splitting the two K chunks)
+    constexpr int NKC = 2 / KS;              // K chunks per wave
+    static_assert(MT * NT * KS == 4, "four waves");
+    constexpr int AROW = (18 * NCI * 2 + 255) / 256 * 256 / 2; // u16 per act row: cells x0 - 1 .. x0 + 16
+    constexpr int APL = 6 * AROW;                               // act rows y0 - 1 .. y0 + 4
+    constexpr int DROW = 16 * NCO, DPL = 4 * DROW;              // dz rows y0 .. y0 + 3
+    constexpr int T_ACT = 6 * 18 * NCG, RA = (T_ACT + 255) / 256; // 16-byte chunks of an act plane
+    constexpr int T_DZ = 4 * 16 * NCGZ;                           // and of a dz plane
+    static_assert(T_DZ <= 256, "one dz chunk per lane");
+    __shared__ __align__(16) u16 act_l[2 * APL];
+    __shared__ __align__(16) u16 dz_l[2 * DPL];
     __shared__ float bsum_l[T_DZ][8];
+    __shared__ float red_l[KS == 2 ? 2 * 27 * 4 * 64 : 1];
     const Geo g = a.geo;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, quad = lane >> 4;
+    const int tile = KS == 1 ? wave : (wave & 1);
+    const int mw = MT == 1 ? 0 : (NT == 1 ? tile : tile >> 1);
+    const int nw = NT == 1 ? 0 : (MT == 1 ? tile : tile & 1);
+    const int kc0 = KS == 1 ? 0 : wave >> 1;
 
-    // Channel rows past CIN / COUTS stay zero.
-    for (int e = tid; e < 9 * NCI * AS; e += 256)
-        if ((e / AS) % NCI >= CIN) act_l[e] = 0;
-    for (int e = tid; e < NCO * DS; e += 256)
-        if (e / DS >= COUTS) dz_l[e] = 0;
+    // Channels past CIN / COUTS stay zero.
+    for (int e = tid; e < 2 * APL; e += 256) act_l[e] = 0;
+    for (int e = tid; e < 2 * DPL; e += 256) dz_l[e] = 0;
+    __syncthreads();
 
-    f32x4 acc[ND][MT][NT];
+    f32x4 acc[27];
 #pragma unroll
-    for (int i = 0; i < ND; ++i)
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int n = 0; n < NT; ++n) acc[i][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 27; ++d) acc[d] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bs[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) bs[c] = 0.f;
-
-    // Four cells (8 channels each, one uint4 per cell) -> 8 channels x 4 cells
-    // (one uint2 per channel).
-    auto transpose_store = [&](const uint4 (&q)[4], u16 *dst, int stride) {
-        const uint32_t *w0 = reinterpret_cast<const uint32_t *>(&q[0]);
-        const uint32_t *w1 = reinterpret_cast<const uint32_t *>(&q[1]);
-        const uint32_t *w2 = reinterpret_cast<const uint32_t *>(&q[2]);
-        const uint32_t *w3 = reinterpret_cast<const uint32_t *>(&q[3]);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int wi = c >> 1;
-            uint2 o;
-            if (c & 1) {
-                o.x = (w0[wi] >> 16) | (w1[wi] & 0xffff0000u);
-                o.y = (w2[wi] >> 16) | (w3[wi] & 0xffff0000u);
-            } else {
-                o.x = (w0[wi] & 0xffffu) | (w1[wi] << 16);
-                o.y = (w2[wi] & 0xffffu) | (w3[wi] << 16);
-            }
-            *reinterpret_cast<uint2 *>(dst + c * stride) = o;
-        }
-    };
 
     const int ntx = g.nx / 16, nty = (g.ny + 3) / 4, ntz = (g.nz + WG_ZC - 1) / WG_ZC;
     const int nitems = ntx * nty * ntz * a.nsamp;
@@ -632,150 +651,148 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         const int x0 = tx * 16, y0 = ty * 4, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
         const size_t sbase = (size_t)smp * g.ncell;
 
-        // act plane p (z0 - 1 <= p <= ze) into ring slot (p - z0 + 1) mod 3:
-        // a task (one of the first T_ACT lanes) loads cells 2 h - 1 .. 2 h + 2
-        // of one row and channel group once, and writes the pair 2 h, 2 h + 1
-        // into all three copies; the dz plane is staged by the last T_DZ
-        // lanes. Loads go out a plane ahead (into registers) and are written
-        // to LDS after the plane before has been multiplied.
-        static_assert(T_ACT + T_DZ <= 256, "one staging task per lane");
-        uint4 qa[4], qd[4];
+        // Chunk v of an act plane: channel group v % NCG of cell (v / NCG) % 18
+        // (x0 - 1 + cell) in row v / (18 NCG) (y0 - 1 + row); chunk t of a dz
+        // plane (lanes t < T_DZ): group t % NCGZ, cell (t / NCGZ) % 16, row
+        // t / (16 NCGZ) (rows past ny contribute zero). Plane p goes to buffer p & 1.
+        uint4 qa[RA], qd = uint4{0u, 0u, 0u, 0u};
         auto load_act = [&](int p) {
-            if (tid < T_ACT) {
-                const int cg = tid % NCG;
-                const int h = (tid / NCG) % 8;
-                const int rr = tid / (8 * NCG);
-                const int y = wrapc(y0 + rr - 1, g.ny);
-                const size_t rowbase = sbase + ((size_t)wrapc(p, g.nz) * g.ny + y) * g.nx;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int x = wrapc(x0 + 2 * h + k - 1, g.nx);
-                    qa[k] = *reinterpret_cast<const uint4 *>(a.act + (rowbase + x) * CIN + 8 * cg);
-                }
+            for (int k = 0; k < RA; ++k) {
+                const int v = min(tid + 256 * k, T_ACT - 1);
+                const int cg = v % NCG, cell = (v / NCG) % 18, row = v / (18 * NCG);
+                const int x = wrapc(x0 + cell - 1, g.nx), y = wrapc(y0 + row - 1, g.ny);
+                qa[k] = *reinterpret_cast<const uint4 *>(a.act + (sbase + ((size_t)wrapc(p, g.nz) * g.ny + y) * g.nx + x) * CIN + 8 * cg);
             }
         };
         auto store_act = [&](int p) {
-            if (tid < T_ACT) {
-                const int slot = (p - z0 + 1) % 3;
-                const int cg = tid % NCG;
-                const int h = (tid / NCG) % 8;
-                const int rr = tid / (8 * NCG);
+            u16 *pl = act_l + (p & 1) * APL;
 #pragma unroll
-                for (int sc = 0; sc < 3; ++sc) {
-                    const uint32_t *w0 = reinterpret_cast<const uint32_t *>(&qa[sc]);
-                    const uint32_t *w1 = reinterpret_cast<const uint32_t *>(&qa[sc + 1]);
-                    u16 *dst = act_l + ((slot * 3 + sc) * NCI + 8 * cg) * AS + rr * 16 + 2 * h;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int wi = c >> 1;
-                        const uint32_t o = (c & 1) ? (w0[wi] >> 16) | (w1[wi] & 0xffff0000u)
-                                                   : (w0[wi] & 0xffffu) | (w1[wi] << 16);
-                        *reinterpret_cast<uint32_t *>(dst + c * AS) = o;
-                    }
+            for (int k = 0; k < RA; ++k) {
+                const int v = tid + 256 * k;
+                if (v < T_ACT) {
+                    const int cg = v % NCG, cell = (v / NCG) % 18, row = v / (18 * NCG);
+                    *reinterpret_cast<uint4 *>(pl + row * AROW + wg_pos<NCI>(cell, 8 * cg)) = qa[k];
                 }
             }
         };
-        // dz plane z (rows past ny contribute zero)
-        const int u = tid - (256 - T_DZ);
         auto load_dz = [&](int z) {
-            if (u >= 0) {
-                const int cg = u % NCGZ;
-                const int g4 = (u / NCGZ) % 4;
-                const int y = y0 + u / (4 * NCGZ);
-                if (y < g.ny) {
-                    const size_t base = sbase + ((size_t)z * g.ny + y) * g.nx + x0 + 4 * g4;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) qd[k] = *reinterpret_cast<const uint4 *>(a.dz + (base + k) * COUTS + 8 * cg);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) qd[k] = uint4{0u, 0u, 0u, 0u};
-                }
+            if (tid < T_DZ) {
+                const int cg = tid % NCGZ, cell = (tid / NCGZ) % 16, y = y0 + tid / (16 * NCGZ);
+                qd = y < g.ny ? *reinterpret_cast<const uint4 *>(a.dz + (sbase + ((size_t)z * g.ny + y) * g.nx + x0 + cell) * COUTS + 8 * cg)
+                              : uint4{0u, 0u, 0u, 0u};
             }
         };
-        auto store_dz = [&]() {
-            if (u >= 0) {
-                const int cg = u % NCGZ;
-                const int g4 = (u / NCGZ) % 4;
-                const int rr = u / (4 * NCGZ);
+        auto store_dz = [&](int z) {
+            if (tid < T_DZ) {
+                const int cg = tid % NCGZ, cell = (tid / NCGZ) % 16, row = tid / (16 * NCGZ);
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd[k]);
+                for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
+                *reinterpret_cast<uint4 *>(dz_l + (z & 1) * DPL + row * DROW + wg_pos<NCO>(cell, 8 * cg)) = qd;
+            }
+        };
+        // dz fragments (K chunk kc0 + c) of planes p - 1, p, p + 1
+        bf16x8 am[NKC], a0[NKC], ap[NKC];
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
+        for (int c = 0; c < NKC; ++c) am[c] = a0[c] = ap[c] = bf16x8{};
+
+        // B fragments of offset (dyo, dxo) from act plane p meet dz planes
+        // p + 1 (z offset -1), p (0) and p - 1 (+1); the fragments of planes
+        // outside [z0, ze) are zero (one code path: the two planes around a
+        // chunk cost 2 / WG_ZC more MFMAs, adding exact zeros).
+        auto mult = [&](int p) {
+            const u16 *pl = act_l + (p & 1) * APL;
+            auto read_b = [&](int e, bf16x8 *b) {
+                const int dyo = e / 3 - 1, dxo = e % 3 - 1;
+#pragma unroll
+                for (int c = 0; c < NKC; ++c)
+                    b[c] = frag_tr<NCI>(pl + (2 * (kc0 + c) + (quad >> 1) + dyo + 1) * AROW, 8 * (quad & 1) + dxo + 1, 16 * nw, col);
+            };
+            // the reads of offset pair e + 1 are issued before the MFMAs of
+            // pair e, and no earlier: two pairs of B fragments are live
+            bf16x8 b[2][NKC];
+            read_b(0, b[0]);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                if (e + 1 < 9) read_b(e + 1, b[(e + 1) & 1]);
+#pragma unroll
+                for (int c = 0; c < NKC; ++c) {
+                    const bf16x8 bv = b[e & 1][c];
+                    acc[e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[c], bv, acc[e], 0, 0, 0);
+                    acc[9 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[c], bv, acc[9 + e], 0, 0, 0);
+                    acc[18 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[c], bv, acc[18 + e], 0, 0, 0);
                 }
-                transpose_store(qd, dz_l + (8 * cg) * DS + rr * 16 + 4 * g4, DS);
+                __builtin_amdgcn_sched_barrier(0);
             }
         };
 
         load_act(z0 - 1);
-        store_act(z0 - 1);
-        load_act(z0);
-        store_act(z0);
-        load_act(z0 + 1);
         load_dz(z0);
-        store_act(z0 + 1);
-        store_dz();
+        store_act(z0 - 1);
+        store_dz(z0);
+        load_act(z0);
+        if (z0 + 1 < ze) load_dz(z0 + 1);
         __syncthreads();
-        for (int z = z0; z < ze; ++z) {
-            if (z + 2 <= ze) load_act(z + 2);
-            if (z + 1 < ze) load_dz(z + 1);
-            bf16x8 af[2][MT];
+        for (int p = z0 - 1; p <= ze; ++p) {
+            // buffers: act plane p and dz plane p + 1 are in LDS; registers
+            // hold act plane p + 1 and dz plane p + 2
+            if (p + 1 <= ze) store_act(p + 1);
+            if (p + 2 < ze) store_dz(p + 2);
+            if (p + 1 < ze) {
+                const u16 *dl = dz_l + ((p + 1) & 1) * DPL;
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+                for (int c = 0; c < NKC; ++c)
+                    ap[c] = frag_tr<NCO>(dl + (2 * (kc0 + c) + (quad >> 1)) * DROW, 8 * (quad & 1), 16 * mw, col);
+            } else {
 #pragma unroll
-                for (int m = 0; m < MT; ++m) af[c][m] = load8(dz_l + (16 * m + col) * DS + 32 * c + 8 * quad);
-#pragma unroll
-            for (int i = 0; i < ND; ++i) {
-                const int d = wave + 4 * i;
-                if (d >= 27) break;
-                const int dzo = d / 9 - 1, dyo = (d / 3) % 3 - 1, dxo = d % 3 - 1;
-                const int slot = (z - z0 + 1 + dzo) % 3;
-                const u16 *bbase = act_l + (slot * 3 + dxo + 1) * NCI * AS + 8 * (quad & 1);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int row = 2 * c + (quad >> 1) + dyo + 1;
-#pragma unroll
-                    for (int n = 0; n < NT; ++n) {
-                        const bf16x8 bv = load8(bbase + (16 * n + col) * AS + row * 16);
-#pragma unroll
-                        for (int m = 0; m < MT; ++m)
-                            acc[i][m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[c][m], bv, acc[i][m][n], 0, 0, 0);
-                    }
-                }
+                for (int c = 0; c < NKC; ++c) ap[c] = bf16x8{};
             }
-            __syncthreads(); // the ring slot of plane z - 1 and the dz plane are rewritten next
-            if (z + 2 <= ze) store_act(z + 2);
-            if (z + 1 < ze) store_dz();
+            if (p + 2 <= ze) load_act(p + 2);
+            if (p + 3 < ze) load_dz(p + 3);
+            mult(p);
             __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NKC; ++c) {
+                am[c] = a0[c];
+                a0[c] = ap[c];
+            }
         }
     }
 
-    // Bias partials: dz staging task t (lane 256 - T_DZ + t) summed channels
-    // 8 (t % NCGZ) + c; fold the tasks of each channel in task order.
-    if (tid >= 256 - T_DZ)
+    // Bias partials: dz staging lane t summed channels 8 (t % NCGZ) + c; fold
+    // the lanes of each channel in lane order.
+    if (tid < T_DZ)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) bsum_l[tid - (256 - T_DZ)][c] = bs[c];
+        for (int c = 0; c < 8; ++c) bsum_l[tid][c] = bs[c];
+    if constexpr (KS == 2) {
+        // the waves of the second K chunk hand their sums to those of the first
+        if (wave >= 2)
+#pragma unroll
+            for (int d = 0; d < 27; ++d)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) red_l[(((wave & 1) * 27 + d) * 4 + j) * 64 + lane] = acc[d][j];
+    }
     __syncthreads();
     if (tid < COUTS) {
         float t = 0.f;
         for (int l = tid / 8; l < T_DZ; l += NCGZ) t += bsum_l[l][tid % 8];
         a.bpart[(size_t)blockIdx.x * 32 + tid] = t;
     }
-    // acc[i][m][n][j]: offset d, co = 16 m + 4 quad + j, ci = 16 n + col.
+    if (KS == 2 && wave >= 2) return;
+    if constexpr (KS == 2) {
+#pragma unroll
+        for (int d = 0; d < 27; ++d)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[d][j] += red_l[(((wave & 1) * 27 + d) * 4 + j) * 64 + lane];
+    }
+    // acc[d][j]: co = 16 mw + 4 quad + j, ci = 16 nw + col
     constexpr int PCO = 16 * MT, PCI = 16 * NT;
     float *part = a.part + (size_t)blockIdx.x * 27 * PCO * PCI;
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
-        const int d = wave + 4 * i;
-        if (d >= 27) break;
+    for (int d = 0; d < 27; ++d)
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int n = 0; n < NT; ++n)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    part[((size_t)d * PCO + 16 * m + 4 * quad + j) * PCI + 16 * n + col] = acc[i][m][n][j];
-    }
+        for (int j = 0; j < 4; ++j) part[((size_t)d * PCO + 16 * mw + 4 * quad + j) * PCI + 16 * nw + col] = acc[d][j];
 }
 
 // grad[W(co, ci, d)] = sum over workgroups of the partials; the first

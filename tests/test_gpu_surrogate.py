@@ -14,8 +14,9 @@ compared element by element with the oracle fed the GPU's own BF16 inputs
     at most 1e-6 absolute;
   - weight and bias gradients: per-workgroup FP32 partials (the chain is the
     workgroup's MFMAs or adds), folded in FP64, rounded once to FP32.
-The shapes (2 samples of 48 x 10 x 40) cover three x-patches, a partial
-y-patch, ten convolution z-chunks and three weight-gradient z-chunks.
+The shapes (2 samples of 48 x 10 x 72) cover three x-patches, a partial
+y-patch, eighteen convolution z-chunks and two weight-gradient z-chunks (64
+planes and a ragged 8).
 
 End to end (forward, loss and gradients from the original inputs), the
 relative L2 errors come from BF16 rounding through four layers and are
@@ -161,7 +162,7 @@ def test_layers_elementwise_full_path_shapes(torch):
     """Every layer's forward, data-gradient, weight- and bias-gradient kernel
     element by element against the oracle on the GPU's own BF16 inputs."""
     from paper_2309_10292_amd.surrogate import Surrogate
-    nz, ny, nx, n = 40, 10, 48, 2
+    nz, ny, nx, n = 72, 10, 48, 2
     shape = (nz, ny, nx)
     p32 = _params(13)
     u, v = _fields(shape, n, 14)
@@ -184,13 +185,17 @@ def test_layers_elementwise_full_path_shapes(torch):
     bb = [b for _, b in params]                    # biases stay FP32
     cl = lambda a: np.moveaxis(a, -1, 0)           # (z, y, x, c) -> (c, z, y, x)
     n_terms = 2 * n * nz * ny * nx
-    # chain lengths: forward / data-gradient MFMAs per output, weight-gradient
-    # MFMAs per workgroup partial, bias-gradient FP32 adds per partial
-    items = (nx // 16) * ((ny + 3) // 4) * ((nz + 15) // 16) * n
+    # chain lengths: forward / data-gradient MFMAs per output; weight-gradient
+    # MFMAs per workgroup partial (work items of 16 x 4 cells by up to 64
+    # planes, two K chunks per plane, plus the add of two waves' sums where
+    # they split the chunks); bias-gradient FP32 adds per partial (one per
+    # staged plane, then the fold over 64 staging lanes)
+    zc_w = 64
+    items = (nx // 16) * ((ny + 3) // 4) * (-(-nz // zc_w)) * n
     per_wg = -(-items // 512)
     gam = lambda nch: 32 * nch * U
-    gam_w = 32 * (per_wg * 16 * 2) * U
-    gam_b = (per_wg * 16 * 4 + 16 + 1) * U
+    gam_w = 32 * (per_wg * min(zc_w, nz) * 2 + 1) * U
+    gam_b = (per_wg * min(zc_w, nz) + 64 + 1) * U
     gW_all = S.unflatten(g.astype(np.float64))
     sums_W = [np.zeros_like(W) for W in Wb]
     sums_b = [np.zeros_like(b) for b in bb]
