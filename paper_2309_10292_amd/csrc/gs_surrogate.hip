@@ -600,6 +600,15 @@ __device__ __forceinline__ bf16x8 frag_tr(const u16 *row, int cell0, int c0, int
     return __builtin_bit_cast(bf16x8, v);
 }
 
+// Workgroup barrier that waits for the wave's LDS operations only: global
+// loads in flight (the next planes' staging) stay in flight across it.
+__device__ __forceinline__ void wg_lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0); vmcnt and expcnt not waited
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 template <int CIN, int COUTS, int MT, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void wgrad_kernel(WgradArgs a)
 {
@@ -651,45 +660,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int x0 = tx * 16, y0 = ty * 4, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
         const size_t sbase = (size_t)smp * g.ncell;
 
+        // Per item, each lane's staging chunks sit at fixed offsets within a
+        // plane (global) and within a buffer (LDS); a plane adds its offset.
         // Chunk v of an act plane: channel group v % NCG of cell (v / NCG) % 18
         // (x0 - 1 + cell) in row v / (18 NCG) (y0 - 1 + row); chunk t of a dz
         // plane (lanes t < T_DZ): group t % NCGZ, cell (t / NCGZ) % 16, row
         // t / (16 NCGZ) (rows past ny contribute zero). Plane p goes to buffer p & 1.
-        uint4 qa[RA], qd = uint4{0u, 0u, 0u, 0u};
-        auto load_act = [&](int p) {
+        const size_t plane_a = (size_t)g.ny * g.nx * CIN, plane_d = (size_t)g.ny * g.nx * COUTS;
+        const u16 *act_s = a.act + sbase * CIN, *dz_s = a.dz + sbase * COUTS;
+        size_t goff_a[RA];
+        int loff_a[RA];
 #pragma unroll
-            for (int k = 0; k < RA; ++k) {
-                const int v = min(tid + 256 * k, T_ACT - 1);
-                const int cg = v % NCG, cell = (v / NCG) % 18, row = v / (18 * NCG);
-                const int x = wrapc(x0 + cell - 1, g.nx), y = wrapc(y0 + row - 1, g.ny);
-                qa[k] = *reinterpret_cast<const uint4 *>(a.act + (sbase + ((size_t)wrapc(p, g.nz) * g.ny + y) * g.nx + x) * CIN + 8 * cg);
-            }
+        for (int k = 0; k < RA; ++k) {
+            const int v = min(tid + 256 * k, T_ACT - 1);
+            const int cg = v % NCG, cell = (v / NCG) % 18, row = v / (18 * NCG);
+            const int x = wrapc(x0 + cell - 1, g.nx), y = wrapc(y0 + row - 1, g.ny);
+            goff_a[k] = ((size_t)y * g.nx + x) * CIN + 8 * cg;
+            loff_a[k] = row * AROW + wg_pos<NCI>(cell, 8 * cg);
+        }
+        const int dcg = tid % NCGZ, dcell = (tid / NCGZ) % 16, drow = tid / (16 * NCGZ);
+        const bool dz_lane = tid < T_DZ, dz_in = dz_lane && y0 + drow < g.ny;
+        // lanes with nothing to stage load a valid chunk of the plane and keep zero
+        const size_t goff_d = dz_in ? ((size_t)(y0 + drow) * g.nx + x0 + dcell) * COUTS + 8 * dcg : (size_t)x0 * COUTS;
+        const int loff_d = drow * DROW + wg_pos<NCO>(dcell, 8 * dcg);
+
+        uint4 qa[RA], qd;
+        auto load_act = [&](int p) {
+            const u16 *src = act_s + (size_t)wrapc(p, g.nz) * plane_a;
+#pragma unroll
+            for (int k = 0; k < RA; ++k) qa[k] = *reinterpret_cast<const uint4 *>(src + goff_a[k]);
         };
         auto store_act = [&](int p) {
             u16 *pl = act_l + (p & 1) * APL;
 #pragma unroll
-            for (int k = 0; k < RA; ++k) {
-                const int v = tid + 256 * k;
-                if (v < T_ACT) {
-                    const int cg = v % NCG, cell = (v / NCG) % 18, row = v / (18 * NCG);
-                    *reinterpret_cast<uint4 *>(pl + row * AROW + wg_pos<NCI>(cell, 8 * cg)) = qa[k];
-                }
-            }
+            for (int k = 0; k < RA; ++k)
+                if (tid + 256 * k < T_ACT) *reinterpret_cast<uint4 *>(pl + loff_a[k]) = qa[k];
         };
         auto load_dz = [&](int z) {
-            if (tid < T_DZ) {
-                const int cg = tid % NCGZ, cell = (tid / NCGZ) % 16, y = y0 + tid / (16 * NCGZ);
-                qd = y < g.ny ? *reinterpret_cast<const uint4 *>(a.dz + (sbase + ((size_t)z * g.ny + y) * g.nx + x0 + cell) * COUTS + 8 * cg)
-                              : uint4{0u, 0u, 0u, 0u};
-            }
+            const uint4 t = *reinterpret_cast<const uint4 *>(dz_s + (size_t)z * plane_d + goff_d);
+            qd = dz_in ? t : uint4{0u, 0u, 0u, 0u};
         };
         auto store_dz = [&](int z) {
-            if (tid < T_DZ) {
-                const int cg = tid % NCGZ, cell = (tid / NCGZ) % 16, row = tid / (16 * NCGZ);
+            if (dz_lane) {
                 const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
-                *reinterpret_cast<uint4 *>(dz_l + (z & 1) * DPL + row * DROW + wg_pos<NCO>(cell, 8 * cg)) = qd;
+                *reinterpret_cast<uint4 *>(dz_l + (z & 1) * DPL + loff_d) = qd;
             }
         };
         // dz fragments (K chunk kc0 + c) of planes p - 1, p, p + 1
@@ -709,16 +725,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 for (int c = 0; c < NKC; ++c)
                     b[c] = frag_tr<NCI>(pl + (2 * (kc0 + c) + (quad >> 1) + dyo + 1) * AROW, 8 * (quad & 1) + dxo + 1, 16 * nw, col);
             };
-            // the reads of offset pair e + 1 are issued before the MFMAs of
-            // pair e, and no earlier: two pairs of B fragments are live
-            bf16x8 b[2][NKC];
-            read_b(0, b[0]);
+            // the reads of offset pair e + LA are issued before the MFMAs of
+            // pair e, and no earlier: LA + 1 pairs of B fragments are live
+            constexpr int LA = NKC == 1 ? 3 : 2;
+            bf16x8 b[LA + 1][NKC];
+#pragma unroll
+            for (int e = 0; e < LA; ++e) read_b(e, b[e]);
 #pragma unroll
             for (int e = 0; e < 9; ++e) {
-                if (e + 1 < 9) read_b(e + 1, b[(e + 1) & 1]);
+                if (e + LA < 9) read_b(e + LA, b[(e + LA) % (LA + 1)]);
 #pragma unroll
                 for (int c = 0; c < NKC; ++c) {
-                    const bf16x8 bv = b[e & 1][c];
+                    const bf16x8 bv = b[e % (LA + 1)][c];
                     acc[e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[c], bv, acc[e], 0, 0, 0);
                     acc[9 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[c], bv, acc[9 + e], 0, 0, 0);
                     acc[18 + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[c], bv, acc[18 + e], 0, 0, 0);
@@ -727,16 +745,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
         };
 
+        // When plane p is multiplied the registers hold act plane p + 1 and
+        // dz plane p + 2, loaded during plane p - 1. Every plane issues the
+        // same loads (plane indices clamped to the chunk) and the barrier
+        // waits for LDS operations only, so the loads stay in flight across
+        // it until their stores.
         load_act(z0 - 1);
         load_dz(z0);
         store_act(z0 - 1);
         store_dz(z0);
         load_act(z0);
-        if (z0 + 1 < ze) load_dz(z0 + 1);
+        load_dz(min(z0 + 1, ze - 1));
         __syncthreads();
         for (int p = z0 - 1; p <= ze; ++p) {
-            // buffers: act plane p and dz plane p + 1 are in LDS; registers
-            // hold act plane p + 1 and dz plane p + 2
             if (p + 1 <= ze) store_act(p + 1);
             if (p + 2 < ze) store_dz(p + 2);
             if (p + 1 < ze) {
@@ -748,16 +769,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                 for (int c = 0; c < NKC; ++c) ap[c] = bf16x8{};
             }
-            if (p + 2 <= ze) load_act(p + 2);
-            if (p + 3 < ze) load_dz(p + 3);
+            load_act(min(p + 2, ze));
+            load_dz(min(p + 3, ze - 1));
             mult(p);
-            __syncthreads();
+            wg_lds_barrier();
 #pragma unroll
             for (int c = 0; c < NKC; ++c) {
                 am[c] = a0[c];
                 a0[c] = ap[c];
             }
         }
+        __syncthreads(); // the loads issued past the chunk's end have landed
     }
 
     // Bias partials: dz staging lane t summed channels 8 (t % NCGZ) + c; fold
