@@ -45,7 +45,8 @@ TB_LANES = {5: 256, 6: 512, 7: 512, 8: 768, 9: 1024}
 # Kernel sources whose change invalidates counter measurements.
 KERNEL_SOURCES = ["paper_2309_10292_amd/csrc/gs_tblock.hip", "paper_2309_10292_amd/csrc/gs_step.hip",
                   "paper_2309_10292_amd/csrc/gs_device.hpp", "paper_2309_10292_amd/csrc/gs_launch.hpp",
-                  "paper_2309_10292_amd/csrc/gs_api.cpp"]
+                  "paper_2309_10292_amd/csrc/gs_tblock_common.hpp", "paper_2309_10292_amd/csrc/gs_api.cpp",
+                  "paper_2309_10292_amd/csrc/gs_internal.hpp"]
 MIN_BLOCKS = 5
 MIN_TIMED_SECONDS = 0.5
 MAX_BLOCKS = 2000

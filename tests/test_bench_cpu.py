@@ -39,6 +39,21 @@ def test_traffic_only_for_the_current_kernel_and_launch(tmp_path):
     assert any("gs_launch.hpp" in f for f in bench.KERNEL_SOURCES)
 
 
+def test_kernel_sources_closed_under_local_includes():
+    """Every library header a hashed source includes is hashed too, so a
+    change to it also invalidates the stored counter bytes."""
+    import os
+    import re
+    hashed = set(bench.KERNEL_SOURCES)
+    for f in bench.KERNEL_SOURCES:
+        d = os.path.dirname(f)
+        with open(os.path.join(bench.ROOT, f)) as fh:
+            for inc in re.findall(r'#include "([^"]+)"', fh.read()):
+                path = os.path.normpath(os.path.join(d, inc))
+                if path.startswith("paper_2309_10292_amd/csrc/"):
+                    assert path in hashed, (f, inc)
+
+
 def test_roofline_fraction_is_of_the_binding_roof():
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9   # 256 x 4 x 16 lanes x 2.4 GHz
     assert bench.alu_ops_per_cell_update("f64", True) == 48
