@@ -158,18 +158,21 @@ def _check(name, got, ref, bound):
     assert worst <= 1.0, (name, worst)
 
 
-def test_layers_elementwise_full_path_shapes(torch):
+@pytest.mark.parametrize("nz, ny, nx, n", [(72, 10, 48, 2), (65, 6, 16, 1)], ids=["72x10x48x2", "65x6x16x1"])
+def test_layers_elementwise_full_path_shapes(torch, nz, ny, nx, n):
     """Every layer's forward, data-gradient, weight- and bias-gradient kernel
-    element by element against the oracle on the GPU's own BF16 inputs."""
+    element by element against the oracle on the GPU's own BF16 inputs.
+    The second shape ends the weight gradient's last z-chunk with a single
+    plane (64 + 1) and the convolutions' with a single plane too, in one
+    x-patch and a two-row last y-patch."""
     from paper_2309_10292_amd.surrogate import Surrogate
-    nz, ny, nx, n = 72, 10, 48, 2
     shape = (nz, ny, nx)
     p32 = _params(13)
     u, v = _fields(shape, n, 14)
     rng = np.random.default_rng(15)
     ut = u + 0.02 * rng.normal(size=u.shape)
     vt = v + 0.02 * rng.normal(size=v.shape)
-    F, k = np.array([0.025, 0.05]), np.array([0.045, 0.065])
+    F, k = np.array([0.025, 0.05])[:n], np.array([0.045, 0.065])[:n]
     f32 = lambda a: a.astype(np.float32).astype(np.float64)
     with Surrogate(nx, ny, nz, max_batch=n, params=p32) as m:
         T = lambda a: torch.from_numpy(a.astype(np.float32)).cuda().contiguous()
