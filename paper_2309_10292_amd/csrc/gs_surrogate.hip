@@ -545,8 +545,10 @@ int conv32p_zc(const Geo &g, int nsamp)
 // over 32 cells (two rows of 16).
 //
 // The workgroups are persistent: each walks work items (a patch of 16 x-cells
-// by 4 y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
-// sums in registers. Act plane p meets dz planes p + 1, p and p - 1 (z offsets
+// by TR y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
+// sums in registers. TR is 4, or 8 for the 32 -> 8 layer: its time goes into
+// staging the 32-channel activation planes, and 8 rows load 10 rows per 8
+// instead of 6 per 4 (at one workgroup per CU, for the registers). Act plane p meets dz planes p + 1, p and p - 1 (z offsets
 // -1, 0, +1), so the loop runs over act planes: while plane p is in LDS, the dz
 // fragments of the three planes it meets are held in registers, and every B
 // fragment read from LDS feeds three MFMAs, one per z offset (a third of the
@@ -559,8 +561,9 @@ int conv32p_zc(const Geo &g, int nsamp)
 // half-wave read distinct banks.
 //
 // Wave w owns one 16 x 16 output tile (co x ci) for all 27 offsets: with
-// four tiles (32 -> 32) for both K chunks of a plane, with two tiles two waves
-// share a tile, split the K chunks, and add their sums at the end. Staging is
+// four tiles (32 -> 32) for all K chunks of a plane (two rows of 16 cells
+// each), with two tiles two waves share a tile, split the K chunks, and add
+// their sums at the end. Staging is
 // double-buffered with one barrier per plane: act plane p + 2 and dz plane
 // p + 3 are loaded into registers while plane p is multiplied and stored into
 // the free buffers at the start of the next plane. The bias gradient (the sum
@@ -609,19 +612,20 @@ __device__ __forceinline__ void wg_lds_barrier()
     __builtin_amdgcn_s_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-template <int CIN, int COUTS, int MT, int NT>
+template <int CIN, int COUTS, int MT, int NT, int TR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void wgrad_kernel(WgradArgs a)
 {
     constexpr int NCI = 16 * NT, NCO = 16 * MT;
     constexpr int NCG = CIN / 8, NCGZ = COUTS / 8;
-    constexpr int KS = MT * NT == 4 ? 1 : 2; // waves per output tile (splitting the two K chunks)
-    constexpr int NKC = 2 / KS;              // K chunks per wave
+    constexpr int KS = MT * NT == 4 ? 1 : 2; // waves per output tile (splitting the K chunks)
+    constexpr int NKC = TR / 2 / KS;         // K chunks (two rows of 16 cells) per wave and plane
+    static_assert(TR % (2 * KS) == 0, "whole K chunks per wave");
     static_assert(MT * NT * KS == 4, "four waves");
     constexpr int AROW = (18 * NCI * 2 + 255) / 256 * 256 / 2; // u16 per act row: cells x0 - 1 .. x0 + 16
-    constexpr int APL = 6 * AROW;                               // act rows y0 - 1 .. y0 + 4
-    constexpr int DROW = 16 * NCO, DPL = 4 * DROW;              // dz rows y0 .. y0 + 3
-    constexpr int T_ACT = 6 * 18 * NCG, RA = (T_ACT + 255) / 256; // 16-byte chunks of an act plane
-    constexpr int T_DZ = 4 * 16 * NCGZ;                           // and of a dz plane
+    constexpr int APL = (TR + 2) * AROW;                        // act rows y0 - 1 .. y0 + TR
+    constexpr int DROW = 16 * NCO, DPL = TR * DROW;             // dz rows y0 .. y0 + TR - 1
+    constexpr int T_ACT = (TR + 2) * 18 * NCG, RA = (T_ACT + 255) / 256; // 16-byte chunks of an act plane
+    constexpr int T_DZ = TR * 16 * NCGZ;                                  // and of a dz plane
     static_assert(T_DZ <= 256, "one dz chunk per lane");
     __shared__ __align__(16) u16 act_l[2 * APL];
     __shared__ __align__(16) u16 dz_l[2 * DPL];
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int tile = KS == 1 ? wave : (wave & 1);
     const int mw = MT == 1 ? 0 : (NT == 1 ? tile : tile >> 1);
     const int nw = NT == 1 ? 0 : (MT == 1 ? tile : tile & 1);
-    const int kc0 = KS == 1 ? 0 : wave >> 1;
+    const int kc0 = KS == 1 ? 0 : (wave >> 1) * NKC;
 
     // Channels past CIN / COUTS stay zero.
     for (int e = tid; e < 2 * APL; e += 256) act_l[e] = 0;
@@ -647,7 +651,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int c = 0; c < 8; ++c) bs[c] = 0.f;
 
-    const int ntx = g.nx / 16, nty = (g.ny + 3) / 4, ntz = (g.nz + WG_ZC - 1) / WG_ZC;
+    const int ntx = g.nx / 16, nty = (g.ny + TR - 1) / TR, ntz = (g.nz + WG_ZC - 1) / WG_ZC;
     const int nitems = ntx * nty * ntz * a.nsamp;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         int r = it;
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         r /= nty;
         const int tz = r % ntz;
         const int smp = r / ntz;
-        const int x0 = tx * 16, y0 = ty * 4, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
+        const int x0 = tx * 16, y0 = ty * TR, z0 = tz * WG_ZC, ze = min(z0 + WG_ZC, g.nz);
         const size_t sbase = (size_t)smp * g.ncell;
 
         // Per item, each lane's staging chunks sit at fixed offsets within a
@@ -1003,11 +1007,11 @@ hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st)
 {
     const int grid = wgrad_blocks();
     if (cin == 32 && couts == 32)
-        hipLaunchKernelGGL((wgrad_kernel<32, 32, 2, 2>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((wgrad_kernel<32, 32, 2, 2, 4>), dim3(grid), dim3(256), 0, st, a);
     else if (cin == 32 && couts == 8)
-        hipLaunchKernelGGL((wgrad_kernel<32, 8, 1, 2>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((wgrad_kernel<32, 8, 1, 2, 8>), dim3(grid), dim3(256), 0, st, a);
     else if (cin == 8 && couts == 32)
-        hipLaunchKernelGGL((wgrad_kernel<8, 32, 2, 1>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((wgrad_kernel<8, 32, 2, 1, 4>), dim3(grid), dim3(256), 0, st, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
