@@ -546,9 +546,10 @@ int conv32p_zc(const Geo &g, int nsamp)
 //
 // The workgroups are persistent: each walks work items (a patch of 16 x-cells
 // by TR y-rows of one sample, through a chunk of WG_ZC planes) and keeps its
-// sums in registers. TR is 4, or 8 for the 32 -> 8 layer: its time goes into
-// staging the 32-channel activation planes, and 8 rows load 10 rows per 8
-// instead of 6 per 4 (at one workgroup per CU, for the registers). Act plane p meets dz planes p + 1, p and p - 1 (z offsets
+// sums in registers. TR is 8 for the layers with 32 input channels, whose
+// staging of 32-channel activation planes costs the most: 8 rows load 10
+// activation rows per 8 instead of 6 per 4 (the 32 -> 8 layer then runs one
+// workgroup per CU, for its registers); the 8 -> 32 layer keeps 4. Act plane p meets dz planes p + 1, p and p - 1 (z offsets
 // -1, 0, +1), so the loop runs over act planes: while plane p is in LDS, the dz
 // fragments of the three planes it meets are held in registers, and every B
 // fragment read from LDS feeds three MFMAs, one per z offset (a third of the
@@ -626,10 +627,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     constexpr int DROW = 16 * NCO, DPL = TR * DROW;             // dz rows y0 .. y0 + TR - 1
     constexpr int T_ACT = (TR + 2) * 18 * NCG, RA = (T_ACT + 255) / 256; // 16-byte chunks of an act plane
     constexpr int T_DZ = TR * 16 * NCGZ;                                  // and of a dz plane
-    static_assert(T_DZ <= 256, "one dz chunk per lane");
+    constexpr int RD = (T_DZ + 255) / 256, TDL = T_DZ < 256 ? T_DZ : 256; // dz chunks per lane, lanes staging dz
+    static_assert(T_DZ <= 256 || T_DZ % 256 == 0, "whole dz rounds");
     __shared__ __align__(16) u16 act_l[2 * APL];
     __shared__ __align__(16) u16 dz_l[2 * DPL];
-    __shared__ float bsum_l[T_DZ][8];
+    __shared__ float bsum_l[TDL][8];
     __shared__ float red_l[KS == 2 ? 2 * 27 * 4 * 64 : 1];
     const Geo g = a.geo;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -682,13 +684,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             goff_a[k] = ((size_t)y * g.nx + x) * CIN + 8 * cg;
             loff_a[k] = row * AROW + wg_pos<NCI>(cell, 8 * cg);
         }
-        const int dcg = tid % NCGZ, dcell = (tid / NCGZ) % 16, drow = tid / (16 * NCGZ);
-        const bool dz_lane = tid < T_DZ, dz_in = dz_lane && y0 + drow < g.ny;
         // lanes with nothing to stage load a valid chunk of the plane and keep zero
-        const size_t goff_d = dz_in ? ((size_t)(y0 + drow) * g.nx + x0 + dcell) * COUTS + 8 * dcg : (size_t)x0 * COUTS;
-        const int loff_d = drow * DROW + wg_pos<NCO>(dcell, 8 * dcg);
+        bool dz_lane[RD], dz_in[RD];
+        size_t goff_d[RD];
+        int loff_d[RD];
+#pragma unroll
+        for (int r = 0; r < RD; ++r) {
+            const int t = tid + 256 * r;
+            const int dcg = t % NCGZ, dcell = (t / NCGZ) % 16, drow = t / (16 * NCGZ);
+            dz_lane[r] = t < T_DZ;
+            dz_in[r] = dz_lane[r] && y0 + drow < g.ny;
+            goff_d[r] = dz_in[r] ? ((size_t)(y0 + drow) * g.nx + x0 + dcell) * COUTS + 8 * dcg : (size_t)x0 * COUTS;
+            loff_d[r] = drow * DROW + wg_pos<NCO>(dcell, 8 * dcg);
+        }
 
-        uint4 qa[RA], qd;
+        uint4 qa[RA], qd[RD];
         auto load_act = [&](int p) {
             const u16 *src = act_s + (size_t)wrapc(p, g.nz) * plane_a;
 #pragma unroll
@@ -701,16 +711,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 if (tid + 256 * k < T_ACT) *reinterpret_cast<uint4 *>(pl + loff_a[k]) = qa[k];
         };
         auto load_dz = [&](int z) {
-            const uint4 t = *reinterpret_cast<const uint4 *>(dz_s + (size_t)z * plane_d + goff_d);
-            qd = dz_in ? t : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int r = 0; r < RD; ++r) {
+                const uint4 t = *reinterpret_cast<const uint4 *>(dz_s + (size_t)z * plane_d + goff_d[r]);
+                qd[r] = dz_in[r] ? t : uint4{0u, 0u, 0u, 0u};
+            }
         };
         auto store_dz = [&](int z) {
-            if (dz_lane) {
-                const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
-                *reinterpret_cast<uint4 *>(dz_l + (z & 1) * DPL + loff_d) = qd;
-            }
+            for (int r = 0; r < RD; ++r)
+                if (dz_lane[r]) { // chunk r of this lane: channel group tid % NCGZ, as every r
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(&qd[r]);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) bs[c] += bf2f((u16)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu)));
+                    *reinterpret_cast<uint4 *>(dz_l + (z & 1) * DPL + loff_d[r]) = qd[r];
+                }
         };
         // dz fragments (K chunk kc0 + c) of planes p - 1, p, p + 1
         bf16x8 am[NKC], a0[NKC], ap[NKC];
@@ -731,7 +746,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             };
             // the reads of offset pair e + LA are issued before the MFMAs of
             // pair e, and no earlier: LA + 1 pairs of B fragments are live
-            constexpr int LA = NKC == 1 ? 3 : 2;
+            // (fewer where a wave takes more K chunks, for the registers)
+            constexpr int LA = NKC == 1 ? 3 : NKC == 2 ? 2 : 1;
             bf16x8 b[LA + 1][NKC];
 #pragma unroll
             for (int e = 0; e < LA; ++e) read_b(e, b[e]);
@@ -786,9 +802,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         __syncthreads(); // the loads issued past the chunk's end have landed
     }
 
-    // Bias partials: dz staging lane t summed channels 8 (t % NCGZ) + c; fold
-    // the lanes of each channel in lane order.
-    if (tid < T_DZ)
+    // Bias partials: dz staging lane t summed channels 8 (t % NCGZ) + c (of
+    // every chunk it stages); fold the lanes of each channel in lane order.
+    if (tid < TDL)
 #pragma unroll
         for (int c = 0; c < 8; ++c) bsum_l[tid][c] = bs[c];
     if constexpr (KS == 2) {
@@ -802,7 +818,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __syncthreads();
     if (tid < COUTS) {
         float t = 0.f;
-        for (int l = tid / 8; l < T_DZ; l += NCGZ) t += bsum_l[l][tid % 8];
+        for (int l = tid / 8; l < TDL; l += NCGZ) t += bsum_l[l][tid % 8];
         a.bpart[(size_t)blockIdx.x * 32 + tid] = t;
     }
     if (KS == 2 && wave >= 2) return;
@@ -1007,7 +1023,7 @@ hipError_t launch_wgrad(int cin, int couts, const WgradArgs &a, hipStream_t st)
 {
     const int grid = wgrad_blocks();
     if (cin == 32 && couts == 32)
-        hipLaunchKernelGGL((wgrad_kernel<32, 32, 2, 2, 4>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((wgrad_kernel<32, 32, 2, 2, 8>), dim3(grid), dim3(256), 0, st, a);
     else if (cin == 32 && couts == 8)
         hipLaunchKernelGGL((wgrad_kernel<32, 8, 1, 2, 8>), dim3(grid), dim3(256), 0, st, a);
     else if (cin == 8 && couts == 32)

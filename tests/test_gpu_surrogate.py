@@ -189,18 +189,18 @@ def test_layers_elementwise_full_path_shapes(torch, nz, ny, nx, n):
     cl = lambda a: np.moveaxis(a, -1, 0)           # (z, y, x, c) -> (c, z, y, x)
     n_terms = 2 * n * nz * ny * nx
     # chain lengths: forward / data-gradient MFMAs per output; weight-gradient
-    # MFMAs per workgroup partial (work items of 16 x 4 cells by up to 64
-    # planes, two K chunks per plane, plus the add of two waves' sums where
-    # they split the chunks; the 32 -> 8 layer's items of 16 x 8 cells are
-    # fewer, with two chunks per wave and plane); bias-gradient FP32 adds per
-    # partial (one per staged plane, then the fold over at most 128 staging
-    # lanes)
+    # MFMAs per workgroup partial (work items of 16 x 4 or 16 x 8 cells by up
+    # to 64 planes, at most four K chunks per wave and plane, plus the add of
+    # two waves' sums where they split the chunks; the 16 x 4 items, counted
+    # here, are the more numerous); bias-gradient FP32 adds per partial (at
+    # most two staged chunks per lane and plane, then the fold over at most
+    # 128 staging lanes)
     zc_w = 64
     items = (nx // 16) * ((ny + 3) // 4) * (-(-nz // zc_w)) * n
     per_wg = -(-items // 512)
     gam = lambda nch: 32 * nch * U
-    gam_w = 32 * (per_wg * min(zc_w, nz) * 2 + 1) * U
-    gam_b = (per_wg * min(zc_w, nz) + 128 + 1) * U
+    gam_w = 32 * (per_wg * min(zc_w, nz) * 4 + 1) * U
+    gam_b = (per_wg * min(zc_w, nz) * 2 + 128 + 1) * U
     gW_all = S.unflatten(g.astype(np.float64))
     sums_W = [np.zeros_like(W) for W in Wb]
     sums_b = [np.zeros_like(b) for b in bb]
