@@ -858,8 +858,11 @@ __global__ __launch_bounds__(256) void wgrad_reduce(const float *__restrict__ pa
         d = e / (cin * cout);
         const size_t stride = (size_t)27 * pco * pci;
         const float *p = part + ((size_t)d * pco + co) * pci;
+        // unrolled so that eight loads are in flight; the adds keep their order
+#pragma unroll 8
         for (int b = j; b < nblk; b += 4) s += p[(size_t)b * stride + ci];
         if (ci < lo_pairs)
+#pragma unroll 8
             for (int b = j; b < nblk; b += 4) s += p[(size_t)b * stride + cin + ci];
     }
     red[j][o] = s;
