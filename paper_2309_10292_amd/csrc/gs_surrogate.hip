@@ -549,27 +549,27 @@ int conv32p_zc(const Geo &g, int nsamp)
 // sums in registers. TR is 8 for the layers with 32 input channels, whose
 // staging of 32-channel activation planes costs the most: 8 rows load 10
 // activation rows per 8 instead of 6 per 4 (the 32 -> 8 layer then runs one
-// workgroup per CU, for its registers); the 8 -> 32 layer keeps 4. Act plane p meets dz planes p + 1, p and p - 1 (z offsets
-// -1, 0, +1), so the loop runs over act planes: while plane p is in LDS, the dz
-// fragments of the three planes it meets are held in registers, and every B
-// fragment read from LDS feeds three MFMAs, one per z offset (a third of the
-// LDS reads of a loop that takes the offsets one by one). For each offset the
-// planes are still added in increasing z. Both operands stay channels-last in
-// LDS, as in memory (16-byte chunks, no transposes on the way in): a fragment
-// (8 cells of one channel per lane) is two transposing LDS reads. Cells 8 .. 15
-// of every 16 have their channel halves swapped (rows of 32 channels) or are
-// moved 4 cells over (rows of 16), so that the two 16-lane groups of a
-// half-wave read distinct banks.
+// workgroup per CU, for its registers); the 8 -> 32 layer keeps 4. Act plane p
+// meets dz planes p + 1, p and p - 1 (z offsets -1, 0, +1), so the loop runs
+// over act planes: while plane p is in LDS, the dz fragments of the three
+// planes it meets are held in registers, and every B fragment read from LDS
+// feeds three MFMAs, one per z offset (a third of the LDS reads of a loop that
+// takes the offsets one by one). For each offset the planes are still added in
+// increasing z. Both operands stay channels-last in LDS, as in memory (16-byte
+// chunks, no transposes on the way in): a fragment (8 cells of one channel per
+// lane) is two transposing LDS reads. Cells 8 .. 15 of every 16 have their
+// channel halves swapped (rows of 32 channels) or are moved 4 cells over (rows
+// of 16), so that the two 16-lane groups of a half-wave read distinct banks.
 //
-// Wave w owns one 16 x 16 output tile (co x ci) for all 27 offsets: with
-// four tiles (32 -> 32) for all K chunks of a plane (two rows of 16 cells
-// each), with two tiles two waves share a tile, split the K chunks, and add
-// their sums at the end. Staging is
-// double-buffered with one barrier per plane: act plane p + 2 and dz plane
-// p + 3 are loaded into registers while plane p is multiplied and stored into
-// the free buffers at the start of the next plane. The bias gradient (the sum
-// of dz over cells) is accumulated while dz is staged. Each workgroup writes
-// its partial sums (padded 16*MT x 16*NT per offset, and 32 bias sums) once.
+// Wave w owns one 16 x 16 output tile (co x ci) for all 27 offsets: with four
+// tiles (32 -> 32) for all K chunks of a plane (two rows of 16 cells each),
+// with two tiles two waves share a tile, split the K chunks, and add their sums
+// at the end. Staging is double-buffered with one barrier per plane: act plane
+// p + 2 and dz plane p + 3 are loaded into registers while plane p is
+// multiplied and stored into the free buffers at the start of the next plane.
+// The bias gradient (the sum of dz over cells) is accumulated while dz is
+// staged. Each workgroup writes its partial sums (padded 16*MT x 16*NT per
+// offset, and 32 bias sums) once.
 constexpr int WG_ZC = 64;
 
 typedef short v4s __attribute__((ext_vector_type(4)));
